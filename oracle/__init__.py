@@ -1,0 +1,226 @@
+"""FP64 brute-force stereo Whitted ray-tracing oracle (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the GPU library or its binding.  The C++
+source (``oracle.cpp``) shares no code with the GPU path.
+
+``render`` returns, per sampled path (path id = eye*H*W + row*W + col):
+radiance [n,3] f64, primary hit t and id, the ray-tree signature (closest-hit id
+per depth, shadow state per depth and light: 0 not cast, 1 occluded, 2 visible)
+and the decision margins used to certify FP32/FP64 disagreements.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# No contraction, no fast-math: every operation is one correctly rounded binary64 operation.
+CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-pthread"]
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.run(["g++", *CXXFLAGS, _SRC, "-o", tmp], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Scene(C.Structure):
+    _fields_ = [
+        ("num_triangles", C.c_int64), ("triangles", C.c_void_p), ("tri_material", C.c_void_p),
+        ("num_spheres", C.c_int32), ("spheres", C.c_void_p), ("sphere_material", C.c_void_p),
+        ("num_planes", C.c_int32), ("planes", C.c_void_p), ("plane_material", C.c_void_p),
+        ("num_materials", C.c_int32), ("materials", C.c_void_p),
+        ("num_lights", C.c_int32), ("lights", C.c_void_p),
+        ("ambient", C.c_float * 3), ("background", C.c_float * 3),
+    ]
+
+
+class _Camera(C.Structure):
+    _fields_ = [
+        ("center", C.c_float * 3), ("forward", C.c_float * 3), ("up", C.c_float * 3),
+        ("hfov_deg", C.c_float), ("baseline", C.c_float), ("convergence", C.c_float),
+        ("width", C.c_int32), ("height", C.c_int32), ("max_depth", C.c_int32),
+    ]
+
+
+class _Output(C.Structure):
+    _fields_ = [
+        ("radiance", C.c_void_p), ("hit_t", C.c_void_p), ("hit_prim", C.c_void_p), ("path_prims", C.c_void_p),
+        ("shadow_state", C.c_void_p), ("hit_margin", C.c_void_p), ("shadow_margin", C.c_void_p),
+        ("shadow_contrib", C.c_void_p), ("ray_counts", C.c_int64 * 3),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        _lib.orc_render.restype = C.c_int
+        _lib.orc_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_void_p, C.c_int64, C.c_int32,
+                                    C.c_int32, C.POINTER(_Output)]
+        _lib.orc_primary_ray.argtypes = [C.POINTER(_Camera), C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+        _lib.orc_primary_ray.restype = None
+        d = C.c_void_p
+        _lib.orc_intersect_triangle.argtypes = [d, d, d, d, d, C.c_double, C.c_double, d, d, d]
+        _lib.orc_intersect_triangle.restype = C.c_int32
+        _lib.orc_intersect_sphere.argtypes = [d, d, d, C.c_double, C.c_double, C.c_double, d]
+        _lib.orc_intersect_sphere.restype = C.c_int32
+        _lib.orc_intersect_plane.argtypes = [d, d, d, C.c_double, C.c_double, C.c_double, d]
+        _lib.orc_intersect_plane.restype = C.c_int32
+        _lib.orc_closest_hits.argtypes = [C.POINTER(_Scene), d, d, C.c_int64, C.c_double, d, d, d, d]
+        _lib.orc_closest_hits.restype = C.c_int32
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class _Held:
+    """Keeps the contiguous arrays a ctypes struct points into alive."""
+
+    def __init__(self):
+        self.arrays = []
+
+    def f32(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        self.arrays.append(a)
+        return a
+
+    def u32(self, a):
+        a = np.ascontiguousarray(a, dtype=np.uint32)
+        self.arrays.append(a)
+        return a
+
+
+def _scene_struct(scene, held: _Held) -> _Scene:
+    s = _Scene()
+    s.num_triangles = scene.triangles.shape[0]
+    s.triangles = _ptr(held.f32(scene.triangles))
+    s.tri_material = _ptr(held.u32(scene.tri_material))
+    s.num_spheres = scene.spheres.shape[0]
+    s.spheres = _ptr(held.f32(scene.spheres))
+    s.sphere_material = _ptr(held.u32(scene.sphere_material))
+    s.num_planes = scene.planes.shape[0]
+    s.planes = _ptr(held.f32(scene.planes))
+    s.plane_material = _ptr(held.u32(scene.plane_material))
+    s.num_materials = scene.materials.shape[0]
+    s.materials = _ptr(held.f32(scene.materials))
+    s.num_lights = scene.lights.shape[0]
+    s.lights = _ptr(held.f32(scene.lights))
+    s.ambient = (C.c_float * 3)(*[float(x) for x in np.asarray(scene.ambient, np.float32)])
+    s.background = (C.c_float * 3)(*[float(x) for x in np.asarray(scene.background, np.float32)])
+    return s
+
+
+def _camera_struct(cam) -> _Camera:
+    c = _Camera()
+    c.center = (C.c_float * 3)(*np.asarray(cam.center, np.float32).tolist())
+    c.forward = (C.c_float * 3)(*np.asarray(cam.forward, np.float32).tolist())
+    c.up = (C.c_float * 3)(*np.asarray(cam.up, np.float32).tolist())
+    c.hfov_deg = float(np.float32(cam.hfov_deg))
+    c.baseline = float(np.float32(cam.baseline))
+    c.convergence = float(np.float32(cam.convergence))
+    c.width, c.height, c.max_depth = int(cam.width), int(cam.height), int(cam.max_depth)
+    return c
+
+
+def default_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def render(scene, cam, samples=None, nthreads=None, fp32_rays=False) -> dict:
+    """Oracle render of the sampled paths (None: every path of both eyes)."""
+    held = _Held()
+    s = _scene_struct(scene, held)
+    c = _camera_struct(cam)
+    if samples is None:
+        n = 2 * cam.width * cam.height
+        samp = None
+    else:
+        samp = np.ascontiguousarray(samples, dtype=np.int64)
+        n = samp.shape[0]
+        if n and (samp.min() < 0 or samp.max() >= 2 * cam.width * cam.height):
+            raise ValueError("sample path id out of range")
+    D1 = cam.max_depth + 1
+    L = scene.lights.shape[0]
+    res = {
+        "radiance": np.zeros((n, 3)), "hit_t": np.zeros(n), "hit_prim": np.zeros(n, np.int32),
+        "path_prims": np.zeros((n, D1), np.int32), "shadow_state": np.zeros((n, D1, L), np.uint8),
+        "hit_margin": np.zeros((n, D1)), "shadow_margin": np.zeros((n, D1, L)),
+        "shadow_contrib": np.zeros((n, D1, L)),
+    }
+    o = _Output()
+    for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state", "hit_margin", "shadow_margin",
+              "shadow_contrib"):
+        setattr(o, k, _ptr(res[k]))
+    rc = lib().orc_render(C.byref(s), C.byref(c), _ptr(samp), n, int(nthreads or default_threads()),
+                          1 if fp32_rays else 0, C.byref(o))
+    if rc != 0:
+        raise ValueError("oracle render rejected its arguments")
+    res["ray_counts"] = np.array(list(o.ray_counts), np.int64)
+    res["samples"] = samp if samp is not None else np.arange(n, dtype=np.int64)
+    return res
+
+
+def primary_ray(cam, eye: int, col: int, row: int):
+    c = _camera_struct(cam)
+    O = np.zeros(3)
+    d = np.zeros(3)
+    lib().orc_primary_ray(C.byref(c), eye, col, row, O.ctypes.data, d.ctypes.data)
+    return O, d
+
+
+def _v(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def intersect_triangle(O, d, v0, v1, v2, tmin=0.0, tmax=np.inf):
+    O, d, v0, v1, v2 = map(_v, (O, d, v0, v1, v2))
+    t, u, v = np.zeros(1), np.zeros(1), np.zeros(1)
+    hit = lib().orc_intersect_triangle(O.ctypes.data, d.ctypes.data, v0.ctypes.data, v1.ctypes.data,
+                                       v2.ctypes.data, tmin, tmax, t.ctypes.data, u.ctypes.data, v.ctypes.data)
+    return bool(hit), float(t[0]), float(u[0]), float(v[0])
+
+
+def intersect_sphere(O, d, c, r, tmin=0.0, tmax=np.inf):
+    O, d, c = map(_v, (O, d, c))
+    t = np.zeros(1)
+    hit = lib().orc_intersect_sphere(O.ctypes.data, d.ctypes.data, c.ctypes.data, float(r), tmin, tmax, t.ctypes.data)
+    return bool(hit), float(t[0])
+
+
+def intersect_plane(O, d, n, dist, tmin=0.0, tmax=np.inf):
+    O, d, n = map(_v, (O, d, n))
+    t = np.zeros(1)
+    hit = lib().orc_intersect_plane(O.ctypes.data, d.ctypes.data, n.ctypes.data, float(dist), tmin, tmax,
+                                    t.ctypes.data)
+    return bool(hit), float(t[0])
+
+
+def closest_hits(scene, O, d, tmin=0.0, exclude=None):
+    """Closest hit (t, prim id, margin) of explicit rays [n,3] against every primitive of the scene."""
+    held = _Held()
+    s = _scene_struct(scene, held)
+    O = _v(O).reshape(-1, 3)
+    d = _v(d).reshape(-1, 3)
+    n = O.shape[0]
+    ex = None if exclude is None else np.ascontiguousarray(exclude, dtype=np.int64)
+    t = np.zeros(n)
+    p = np.zeros(n, np.int64)
+    m = np.zeros(n)
+    lib().orc_closest_hits(C.byref(s), O.ctypes.data, d.ctypes.data, n, float(tmin), _ptr(ex), t.ctypes.data,
+                           p.ctypes.data, m.ctypes.data)
+    return t, p, m

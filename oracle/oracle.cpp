@@ -1,0 +1,602 @@
+// Stereo Whitted ray-tracing oracle: plain, slow, FP64, brute force.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+// baseline leg of the benchmark load this library.  It shares no code, header
+// or constant with the GPU library, and the GPU library never calls it.
+//
+// What it computes (the paper, Sections 2-3): a stereo pair is two projections
+// of one scene, one from each of the observer's eyes ("double rendering"), each
+// synthesised by backward ray tracing, with every pixel's rays independent of
+// every other pixel's.  The paper names no camera, shading model or recursion;
+// the readings taken here are:
+//   * an off-axis stereo pair: eyes at C -+ (B/2) r, pixel-centre rays, image
+//     centres converging at distance Z0 along the forward axis;
+//   * Whitted recursion without refraction: a closest hit, Phong lighting
+//     (kd N.L + ks max(0, R.V)^n, R = 2(N.L)N - L, no distance falloff) from
+//     every point light that a shadow ray finds unoccluded, an ambient term
+//     ambient*kd, and a mirror ray weighted by kr up to a reflection depth D;
+//   * every closest-hit and shadow query answered by testing EVERY primitive
+//     (Moller-Trumbore triangles, spheres, planes); ties in t go to the smaller
+//     primitive id; secondary rays start at t > 1e-4 and skip the primitive
+//     they leave.
+// All arithmetic is IEEE binary64, round-to-nearest, built without
+// contraction or fast-math.  Inputs are the FP32 scene arrays and camera
+// fields, widened exactly.
+//
+// Besides radiance the oracle returns the ray-tree signature (closest-hit id
+// per depth, shadow state per depth and light) and, for each decision, a
+// margin: how far the inputs sit from flipping it.  Tests use the margins to
+// certify pixels where FP32 and FP64 legitimately choose differently.
+
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <thread>
+#include <vector>
+
+namespace {
+
+struct V3 {
+  double x, y, z;
+};
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline V3 mul(V3 a, V3 b) { return {a.x * b.x, a.y * b.y, a.z * b.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double length(V3 a) { return std::sqrt(dot(a, a)); }
+inline V3 normalize(V3 a) { return (1.0 / length(a)) * a; }
+inline V3 load3f(const float* p) { return {double(p[0]), double(p[1]), double(p[2])}; }
+inline V3 round_f32(V3 a) { return {double(float(a.x)), double(float(a.y)), double(float(a.z))}; }
+
+const double kInf = std::numeric_limits<double>::infinity();
+const double kSecondaryTmin = 1e-4;  // self-intersection offset for spawned rays (scene units)
+const double kNearMiss = 1e-2;       // margins above this are not recorded
+
+}  // namespace
+
+extern "C" {
+
+typedef struct {
+  int64_t num_triangles;
+  const float* triangles;  // [T][3][3]
+  const uint32_t* tri_material;
+  int32_t num_spheres;
+  const float* spheres;  // [S][4] centre, radius
+  const uint32_t* sphere_material;
+  int32_t num_planes;
+  const float* planes;  // [P][4] normal, offset (n.x = d)
+  const uint32_t* plane_material;
+  int32_t num_materials;
+  const float* materials;  // [M][10] kd, ks, kr, shininess
+  int32_t num_lights;
+  const float* lights;  // [L][6] position, intensity
+  float ambient[3];
+  float background[3];
+} orc_scene;
+
+typedef struct {
+  float center[3], forward[3], up[3];
+  float hfov_deg, baseline, convergence;
+  int32_t width, height, max_depth;
+} orc_camera;
+
+typedef struct {
+  double* radiance;         // [n][3]
+  double* hit_t;            // [n] primary t, +inf on a miss
+  int32_t* hit_prim;        // [n] primary id, -1 on a miss
+  int32_t* path_prims;      // [n][D+1] closest-hit id per depth; -1 miss, -2 ray not spawned
+  uint8_t* shadow_state;    // [n][D+1][L] 0 not cast, 1 occluded, 2 visible
+  double* hit_margin;       // [n][D+1] closest-hit decision margin (inf when not spawned)
+  double* shadow_margin;    // [n][D+1][L] cast and occlusion decision margin
+  double* shadow_contrib;   // [n][D+1][L] radiance the light's decision is worth at the pixel
+  int64_t ray_counts[3];    // out: primary, reflection, shadow rays traced
+} orc_output;
+
+}  // extern "C"
+
+namespace {
+
+struct Tri {
+  V3 v0, e1, e2;
+};
+
+struct Scene {
+  std::vector<Tri> tris;
+  std::vector<uint32_t> tri_mat;
+  std::vector<V3> sph_c;
+  std::vector<double> sph_r;
+  std::vector<uint32_t> sph_mat;
+  std::vector<V3> pl_n;
+  std::vector<double> pl_d;
+  std::vector<uint32_t> pl_mat;
+  struct Mat {
+    V3 kd, ks, kr;
+    double n;
+  };
+  std::vector<Mat> mats;
+  struct Light {
+    V3 pos, I;
+  };
+  std::vector<Light> lights;
+  V3 ambient, background;
+  int64_t T = 0, S = 0, P = 0;
+};
+
+Scene load_scene(const orc_scene* s) {
+  Scene sc;
+  sc.T = s->num_triangles;
+  sc.S = s->num_spheres;
+  sc.P = s->num_planes;
+  sc.tris.resize(size_t(sc.T));
+  for (int64_t i = 0; i < sc.T; ++i) {
+    const float* p = s->triangles + 9 * i;
+    V3 a = load3f(p), b = load3f(p + 3), c = load3f(p + 6);
+    sc.tris[size_t(i)] = {a, b - a, c - a};
+  }
+  sc.tri_mat.assign(s->tri_material, s->tri_material + sc.T);
+  for (int64_t i = 0; i < sc.S; ++i) {
+    sc.sph_c.push_back(load3f(s->spheres + 4 * i));
+    sc.sph_r.push_back(double(s->spheres[4 * i + 3]));
+    sc.sph_mat.push_back(s->sphere_material[i]);
+  }
+  for (int64_t i = 0; i < sc.P; ++i) {
+    sc.pl_n.push_back(load3f(s->planes + 4 * i));
+    sc.pl_d.push_back(double(s->planes[4 * i + 3]));
+    sc.pl_mat.push_back(s->plane_material[i]);
+  }
+  for (int i = 0; i < s->num_materials; ++i) {
+    const float* m = s->materials + 10 * i;
+    sc.mats.push_back({load3f(m), load3f(m + 3), load3f(m + 6), double(m[9])});
+  }
+  for (int i = 0; i < s->num_lights; ++i) {
+    const float* l = s->lights + 6 * i;
+    sc.lights.push_back({load3f(l), load3f(l + 3)});
+  }
+  sc.ambient = load3f(s->ambient);
+  sc.background = load3f(s->background);
+  return sc;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Ray-primitive tests.  Each returns the parametric distance of the candidate
+// intersection in *t and whether it is accepted for t in (tmin, tmax).
+// ---------------------------------------------------------------------------------------------
+
+// Moller & Trumbore (1997): solve O + t d = v0 + u e1 + v e2 by Cramer's rule.
+// Closed triangle (inclusive edges); only det == 0 is rejected.
+// *margin gets the signed barycentric distance to the nearest edge, min(u, v, 1-u-v),
+// times the sine of the ray's angle to the plane (how far, in relative terms,
+// the ray passes from flipping the inside/outside decision).
+inline bool hit_triangle(const Tri& tr, V3 O, V3 d, double tmin, double tmax, double* t, double* u_out,
+                         double* v_out, double* margin) {
+  V3 Tv = O - tr.v0;
+  V3 P = cross(d, tr.e2);
+  double det = dot(tr.e1, P);
+  *margin = kInf;
+  if (det == 0.0) return false;
+  double u = dot(Tv, P) / det;
+  V3 Q = cross(Tv, tr.e1);
+  double v = dot(d, Q) / det;
+  double tt = dot(tr.e2, Q) / det;
+  *t = tt;
+  *u_out = u;
+  *v_out = v;
+  double m = std::fmin(u, std::fmin(v, 1.0 - u - v));
+  double sin_angle = std::fabs(det) / (length(cross(tr.e1, tr.e2)) * length(d));
+  *margin = m * sin_angle;
+  return u >= 0.0 && v >= 0.0 && u + v <= 1.0 && tt > tmin && tt < tmax;
+}
+
+// Sphere with unit-length d: b = -oc.d is the foot of the perpendicular from the
+// centre, h^2 = |oc + b d|^2 its squared distance, disc = r^2 - h^2; roots b -+ sqrt(disc).
+inline bool hit_sphere(V3 c, double r, V3 O, V3 d, double tmin, double tmax, double* t, double* margin) {
+  V3 oc = O - c;
+  double b = -dot(oc, d);
+  V3 foot = oc + b * d;
+  double h2 = dot(foot, foot);
+  double disc = r * r - h2;
+  *margin = disc / (r * r);
+  if (disc < 0.0) {
+    *t = b;  // closest approach, so that a near miss in front is seen as one
+    return false;
+  }
+  double s = std::sqrt(disc);
+  double t0 = b - s, t1 = b + s;
+  if (t0 > tmin && t0 < tmax) {
+    *t = t0;
+    return true;
+  }
+  if (t1 > tmin && t1 < tmax) {
+    *t = t1;
+    return true;
+  }
+  return false;
+}
+
+inline bool hit_plane(V3 n, double dist, V3 O, V3 d, double tmin, double tmax, double* t, double* margin) {
+  double nd = dot(n, d);
+  *margin = std::fabs(nd) / (length(n) * length(d));
+  if (nd == 0.0) return false;
+  double tt = (dist - dot(n, O)) / nd;
+  *t = tt;
+  return tt > tmin && tt < tmax;
+}
+
+struct Hit {
+  double t = kInf;
+  int64_t prim = -1;
+  double margin = kInf;
+};
+
+// Relative distance of a candidate t from an interval end point.
+inline double t_margin(double t, double edge) {
+  if (edge == 0.0 || !std::isfinite(edge)) return kInf;
+  return std::fabs(t - edge) / std::fabs(edge);
+}
+
+// Closest hit over every primitive: minimum t, exact ties to the smaller id.
+// The decision margin is the smallest of: the winner's inside margin, the
+// outside margin of every near-missed primitive lying in front of the winner,
+// the relative t gap to the runner-up, and the distance of any candidate t from tmin.
+Hit closest_hit(const Scene& sc, V3 O, V3 d, double tmin, int64_t exclude) {
+  Hit best;
+  double second_t = kInf;
+  struct Near {
+    double t, m;
+  };
+  std::vector<Near> near;
+  auto consider = [&](int64_t id, bool hit, double t, double m) {
+    if (std::fabs(m) < kNearMiss && t > tmin * (1.0 - kNearMiss)) near.push_back({t, std::fabs(m)});
+    if (tmin > 0.0 && std::isfinite(t) && t_margin(t, tmin) < kNearMiss) near.push_back({t, t_margin(t, tmin)});
+    if (!hit) return;
+    if (t < best.t || (t == best.t && id < best.prim)) {
+      if (best.prim >= 0) second_t = std::fmin(second_t, best.t);
+      best.t = t;
+      best.prim = id;
+    } else {
+      second_t = std::fmin(second_t, t);
+    }
+  };
+  for (int64_t i = 0; i < sc.T; ++i) {
+    if (i == exclude) continue;
+    double t = kInf, u, v, m;
+    bool h = hit_triangle(sc.tris[size_t(i)], O, d, tmin, kInf, &t, &u, &v, &m);
+    consider(i, h, t, m);
+  }
+  for (int64_t i = 0; i < sc.S; ++i) {
+    int64_t id = sc.T + i;
+    if (id == exclude) continue;
+    double t = kInf, m;
+    bool h = hit_sphere(sc.sph_c[size_t(i)], sc.sph_r[size_t(i)], O, d, tmin, kInf, &t, &m);
+    consider(id, h, t, m);
+  }
+  for (int64_t i = 0; i < sc.P; ++i) {
+    int64_t id = sc.T + sc.S + i;
+    if (id == exclude) continue;
+    double t = kInf, m;
+    bool h = hit_plane(sc.pl_n[size_t(i)], sc.pl_d[size_t(i)], O, d, tmin, kInf, &t, &m);
+    consider(id, h, t, m);
+  }
+  double margin = kInf;
+  double limit = std::isfinite(best.t) ? best.t * (1.0 + kNearMiss) : kInf;
+  for (const Near& n : near)
+    if (n.t <= limit) margin = std::fmin(margin, n.m);
+  if (best.prim >= 0 && std::isfinite(second_t)) margin = std::fmin(margin, (second_t - best.t) / best.t);
+  best.margin = margin;
+  return best;
+}
+
+// Occlusion: does any primitive other than `exclude` intersect for t in (tmin, tmax)?
+// Tests every primitive (no early exit) so that the decision margin is complete.
+bool any_hit(const Scene& sc, V3 O, V3 d, double tmin, double tmax, int64_t exclude, double* margin_out) {
+  bool occluded = false;
+  double margin = kInf;
+  auto consider = [&](bool hit, double t, double m) {
+    bool in_range = t > tmin * (1.0 - kNearMiss) && t < tmax * (1.0 + kNearMiss);
+    if (in_range) margin = std::fmin(margin, std::fabs(m));
+    if (std::isfinite(t)) {
+      if (t_margin(t, tmin) < kNearMiss) margin = std::fmin(margin, t_margin(t, tmin));
+      if (t_margin(t, tmax) < kNearMiss) margin = std::fmin(margin, t_margin(t, tmax));
+    }
+    occluded = occluded || hit;
+  };
+  for (int64_t i = 0; i < sc.T; ++i) {
+    if (i == exclude) continue;
+    double t = kInf, u, v, m;
+    bool h = hit_triangle(sc.tris[size_t(i)], O, d, tmin, tmax, &t, &u, &v, &m);
+    consider(h, t, m);
+  }
+  for (int64_t i = 0; i < sc.S; ++i) {
+    int64_t id = sc.T + i;
+    if (id == exclude) continue;
+    double t = kInf, m;
+    bool h = hit_sphere(sc.sph_c[size_t(i)], sc.sph_r[size_t(i)], O, d, tmin, tmax, &t, &m);
+    consider(h, t, m);
+  }
+  for (int64_t i = 0; i < sc.P; ++i) {
+    int64_t id = sc.T + sc.S + i;
+    if (id == exclude) continue;
+    double t = kInf, m;
+    bool h = hit_plane(sc.pl_n[size_t(i)], sc.pl_d[size_t(i)], O, d, tmin, tmax, &t, &m);
+    consider(h, t, m);
+  }
+  *margin_out = margin;
+  return occluded;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Stereo camera (off-axis pair)
+// ---------------------------------------------------------------------------------------------
+
+struct Camera {
+  V3 C, f, r, u;
+  double fpx, cx, cy, B, Z0;
+  int W, H, D;
+};
+
+Camera make_camera(const orc_camera* c) {
+  Camera cam;
+  cam.C = load3f(c->center);
+  cam.f = normalize(load3f(c->forward));
+  cam.r = normalize(cross(load3f(c->up), cam.f));
+  cam.u = cross(cam.f, cam.r);
+  double half = 0.5 * double(c->hfov_deg) * M_PI / 180.0;
+  cam.W = c->width;
+  cam.H = c->height;
+  cam.D = c->max_depth;
+  cam.fpx = (0.5 * double(cam.W)) / std::tan(half);
+  cam.cx = 0.5 * double(cam.W);
+  cam.cy = 0.5 * double(cam.H);
+  cam.B = double(c->baseline);
+  cam.Z0 = double(c->convergence);
+  return cam;
+}
+
+// Eye e (0 left, 1 right) sits at C + s_e r with s = -+B/2; the ray through the
+// centre of pixel (i, j) (column left to right, row top to bottom).  With a
+// positive convergence distance the frustum is sheared by -s_e/Z0 so that the
+// image centres of both eyes meet at C + Z0 f.
+void primary_ray(const Camera& cam, int eye, int i, int j, V3* O, V3* d) {
+  double s = (eye == 0 ? -0.5 : 0.5) * cam.B;
+  *O = cam.C + s * cam.r;
+  double a = (double(i) + 0.5 - cam.cx) / cam.fpx;
+  if (cam.Z0 > 0.0) a -= s / cam.Z0;
+  double b = -(double(j) + 0.5 - cam.cy) / cam.fpx;
+  *d = normalize(cam.f + a * cam.r + b * cam.u);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Whitted recursion
+// ---------------------------------------------------------------------------------------------
+
+struct PathRecord {
+  V3 radiance;
+  double hit_t;
+  int32_t hit_prim;
+  int32_t* path_prims;
+  uint8_t* shadow_state;
+  double* hit_margin;
+  double* shadow_margin;
+  double* shadow_contrib;
+  int64_t n_refl = 0, n_shadow = 0;
+};
+
+struct Tracer {
+  const Scene& sc;
+  int D;
+  int L;
+  bool fp32_rays;
+
+  uint32_t material_of(int64_t prim) const {
+    if (prim < sc.T) return sc.tri_mat[size_t(prim)];
+    if (prim < sc.T + sc.S) return sc.sph_mat[size_t(prim - sc.T)];
+    return sc.pl_mat[size_t(prim - sc.T - sc.S)];
+  }
+
+  V3 geometric_normal(int64_t prim, V3 P) const {
+    if (prim < sc.T) {
+      const Tri& t = sc.tris[size_t(prim)];
+      return normalize(cross(t.e1, t.e2));
+    }
+    if (prim < sc.T + sc.S) {
+      size_t k = size_t(prim - sc.T);
+      return (1.0 / sc.sph_r[k]) * (P - sc.sph_c[k]);
+    }
+    return normalize(sc.pl_n[size_t(prim - sc.T - sc.S)]);
+  }
+
+  // Radiance arriving along ray (O, d) at recursion depth `depth`.
+  V3 trace(V3 O, V3 d, int depth, double tmin, int64_t exclude, V3 throughput, PathRecord& rec) const {
+    if (fp32_rays) {
+      O = round_f32(O);
+      d = round_f32(d);
+    }
+    Hit h = closest_hit(sc, O, d, tmin, exclude);
+    rec.path_prims[depth] = int32_t(h.prim);
+    rec.hit_margin[depth] = h.margin;
+    if (depth == 0) {
+      rec.hit_t = h.t;
+      rec.hit_prim = int32_t(h.prim);
+    }
+    if (h.prim < 0) return sc.background;
+
+    V3 P = O + h.t * d;
+    V3 Ng = geometric_normal(h.prim, P);
+    V3 N = dot(Ng, d) > 0.0 ? -1.0 * Ng : Ng;
+    V3 V = -1.0 * d;
+    const Scene::Mat& m = sc.mats[material_of(h.prim)];
+
+    V3 Lo = mul(sc.ambient, m.kd);
+    for (int l = 0; l < L; ++l) {
+      const Scene::Light& lt = sc.lights[size_t(l)];
+      V3 Lv = lt.pos - P;
+      double dist = length(Lv);
+      V3 Ld = (1.0 / dist) * Lv;
+      double ndl = dot(N, Ld);
+      size_t k = size_t(depth) * size_t(L) + size_t(l);
+      double cast_margin = std::fabs(ndl);
+      if (dist > kSecondaryTmin && ndl > 0.0) {
+        V3 R = (2.0 * ndl) * N - Ld;
+        double rv = std::fmax(0.0, dot(R, V));
+        double spec = std::pow(rv, m.n);
+        V3 term = mul(lt.I, ndl * m.kd + spec * m.ks);
+        V3 w = mul(term, throughput);
+        rec.shadow_contrib[k] = std::fmax(std::fabs(w.x), std::fmax(std::fabs(w.y), std::fabs(w.z)));
+        double occ_margin;
+        V3 So = P, Sd = Ld;
+        if (fp32_rays) {
+          So = round_f32(So);
+          Sd = round_f32(Sd);
+        }
+        bool occ = any_hit(sc, So, Sd, kSecondaryTmin, dist, h.prim, &occ_margin);
+        rec.n_shadow++;
+        rec.shadow_margin[k] = std::fmin(cast_margin, occ_margin);
+        rec.shadow_state[k] = occ ? 1 : 2;
+        if (!occ) Lo = Lo + term;
+      } else {
+        // Not cast.  Its worth is the jump the Phong term makes at N.L = 0.
+        double rv = std::fmax(0.0, dot(-1.0 * Ld, V));
+        V3 w = mul(mul(lt.I, std::pow(rv, m.n) * m.ks), throughput);
+        rec.shadow_contrib[k] = std::fmax(std::fabs(w.x), std::fmax(std::fabs(w.y), std::fabs(w.z)));
+        rec.shadow_margin[k] = cast_margin;
+        rec.shadow_state[k] = 0;
+      }
+    }
+    bool reflective = m.kr.x != 0.0 || m.kr.y != 0.0 || m.kr.z != 0.0;
+    if (depth < D && reflective) {
+      V3 r = normalize(d - (2.0 * dot(d, N)) * N);
+      rec.n_refl++;
+      V3 Li = trace(P, r, depth + 1, kSecondaryTmin, h.prim, mul(throughput, m.kr), rec);
+      Lo = Lo + mul(m.kr, Li);
+    }
+    return Lo;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+// Renders the sampled paths (path id = eye*H*W + row*W + col; NULL = all 2*H*W
+// of them) with `nthreads` worker threads pulling rows of work dynamically.
+// Returns 0 on success, -1 on invalid arguments.
+int orc_render(const orc_scene* scene_in, const orc_camera* cam_in, const int64_t* samples, int64_t n,
+               int32_t nthreads, int32_t fp32_rays, orc_output* out) {
+  if (!scene_in || !cam_in || !out || cam_in->width <= 0 || cam_in->height <= 0 || cam_in->max_depth < 0)
+    return -1;
+  Scene sc = load_scene(scene_in);
+  Camera cam = make_camera(cam_in);
+  const int64_t HW = int64_t(cam.W) * cam.H;
+  const int64_t total = samples ? n : 2 * HW;
+  const int D = cam.D;
+  const int L = int(sc.lights.size());
+  Tracer tracer{sc, D, L, fp32_rays != 0};
+  std::atomic<int64_t> next{0}, n_refl{0}, n_shadow{0};
+  const int64_t chunk = 4;
+  auto worker = [&]() {
+    int64_t my_refl = 0, my_shadow = 0;
+    for (;;) {
+      int64_t start = next.fetch_add(chunk);
+      if (start >= total) break;
+      int64_t end = std::min(total, start + chunk);
+      for (int64_t s = start; s < end; ++s) {
+        int64_t pid = samples ? samples[s] : s;
+        int eye = int(pid / HW);
+        int64_t px = pid % HW;
+        int row = int(px / cam.W), col = int(px % cam.W);
+        PathRecord rec;
+        rec.path_prims = out->path_prims + s * (D + 1);
+        rec.shadow_state = out->shadow_state + s * (D + 1) * L;
+        rec.hit_margin = out->hit_margin + s * (D + 1);
+        rec.shadow_margin = out->shadow_margin + s * (D + 1) * L;
+        rec.shadow_contrib = out->shadow_contrib + s * (D + 1) * L;
+        for (int k = 0; k <= D; ++k) {
+          rec.path_prims[k] = -2;
+          rec.hit_margin[k] = kInf;
+        }
+        for (int k = 0; k < (D + 1) * L; ++k) {
+          rec.shadow_state[k] = 0;
+          rec.shadow_margin[k] = kInf;
+          rec.shadow_contrib[k] = 0.0;
+        }
+        V3 O, d;
+        primary_ray(cam, eye, col, row, &O, &d);
+        V3 Lr = tracer.trace(O, d, 0, 0.0, -1, V3{1.0, 1.0, 1.0}, rec);
+        out->radiance[3 * s + 0] = Lr.x;
+        out->radiance[3 * s + 1] = Lr.y;
+        out->radiance[3 * s + 2] = Lr.z;
+        out->hit_t[s] = rec.hit_t;
+        out->hit_prim[s] = rec.hit_prim;
+        my_refl += rec.n_refl;
+        my_shadow += rec.n_shadow;
+      }
+    }
+    n_refl += my_refl;
+    n_shadow += my_shadow;
+  };
+  int nt = nthreads > 0 ? nthreads : 1;
+  std::vector<std::thread> pool;
+  for (int i = 1; i < nt; ++i) pool.emplace_back(worker);
+  worker();
+  for (auto& t : pool) t.join();
+  out->ray_counts[0] = total;
+  out->ray_counts[1] = n_refl.load();
+  out->ray_counts[2] = n_shadow.load();
+  return 0;
+}
+
+// Single primary ray, for camera checks.
+void orc_primary_ray(const orc_camera* c, int32_t eye, int32_t col, int32_t row, double* O, double* d) {
+  Camera cam = make_camera(c);
+  V3 o, dd;
+  primary_ray(cam, eye, col, row, &o, &dd);
+  O[0] = o.x, O[1] = o.y, O[2] = o.z;
+  d[0] = dd.x, d[1] = dd.y, d[2] = dd.z;
+}
+
+int32_t orc_intersect_triangle(const double* O, const double* d, const double* v0, const double* v1,
+                               const double* v2, double tmin, double tmax, double* t, double* u, double* v) {
+  V3 a{v0[0], v0[1], v0[2]}, b{v1[0], v1[1], v1[2]}, c{v2[0], v2[1], v2[2]};
+  Tri tr{a, b - a, c - a};
+  double m;
+  *t = kInf;
+  return hit_triangle(tr, V3{O[0], O[1], O[2]}, V3{d[0], d[1], d[2]}, tmin, tmax, t, u, v, &m) ? 1 : 0;
+}
+
+int32_t orc_intersect_sphere(const double* O, const double* d, const double* c, double r, double tmin, double tmax,
+                             double* t) {
+  double m;
+  *t = kInf;
+  if (hit_sphere(V3{c[0], c[1], c[2]}, r, V3{O[0], O[1], O[2]}, V3{d[0], d[1], d[2]}, tmin, tmax, t, &m)) return 1;
+  *t = kInf;
+  return 0;
+}
+
+int32_t orc_intersect_plane(const double* O, const double* d, const double* n, double dist, double tmin, double tmax,
+                            double* t) {
+  double m;
+  *t = kInf;
+  return hit_plane(V3{n[0], n[1], n[2]}, dist, V3{O[0], O[1], O[2]}, V3{d[0], d[1], d[2]}, tmin, tmax, t, &m) ? 1
+                                                                                                              : 0;
+}
+
+// Closest hit / occlusion of explicit rays against a scene (batch).  d need not be
+// unit length for triangles and planes; spheres require unit d.
+int32_t orc_closest_hits(const orc_scene* scene_in, const double* O, const double* d, int64_t n, double tmin,
+                         const int64_t* exclude, double* t_out, int64_t* prim_out, double* margin_out) {
+  Scene sc = load_scene(scene_in);
+  for (int64_t i = 0; i < n; ++i) {
+    Hit h = closest_hit(sc, V3{O[3 * i], O[3 * i + 1], O[3 * i + 2]}, V3{d[3 * i], d[3 * i + 1], d[3 * i + 2]}, tmin,
+                        exclude ? exclude[i] : -1);
+    t_out[i] = h.t;
+    prim_out[i] = h.prim;
+    if (margin_out) margin_out[i] = h.margin;
+  }
+  return 0;
+}
+
+}  // extern "C"
