@@ -1,0 +1,493 @@
+// C ABI of the stereo ray tracer: argument validation, memory planning, timers and the
+// host-side driving of the device passes.  No kernels live here.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rt_internal.h"
+
+namespace srt {
+
+struct Scene {
+  DevScene dev;
+  int device;
+  rt_scene_info info;
+};
+
+struct TimerImpl {
+  struct Rec {
+    int stage;
+    hipEvent_t start, end;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t pending_start = nullptr;
+  int pending_stage = -1;
+  hipError_t error = hipSuccess;
+
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      error = r;
+      return nullptr;
+    }
+    return e;
+  }
+};
+
+void timer_begin(TimerImpl* t, int stage, hipStream_t s) {
+  hipEvent_t e = t->take();
+  if (!e) return;
+  hipError_t r = hipEventRecord(e, s);
+  if (r != hipSuccess) t->error = r;
+  t->pending_start = e;
+  t->pending_stage = stage;
+}
+
+void timer_end(TimerImpl* t, int stage, hipStream_t s) {
+  if (!t->pending_start || t->pending_stage != stage) return;
+  hipEvent_t e = t->take();
+  if (!e) return;
+  hipError_t r = hipEventRecord(e, s);
+  if (r != hipSuccess) t->error = r;
+  t->recs.push_back({stage, t->pending_start, e});
+  t->pending_start = nullptr;
+  t->pending_stage = -1;
+}
+
+}  // namespace srt
+
+struct rt_scene_s : srt::Scene {};
+struct rt_timer_s : srt::TimerImpl {};
+
+namespace {
+
+thread_local std::string g_error;
+
+rt_status fail(rt_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return s;
+}
+
+rt_status ok() {
+  g_error.clear();
+  return RT_OK;
+}
+
+rt_status hip_fail(hipError_t e, const char* what) {
+  return fail(RT_ERR_DEVICE, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+rt_status validate_desc(const rt_scene_desc* d) {
+  if (!d) return fail(RT_ERR_INVALID_ARGUMENT, "scene descriptor is NULL");
+  if (d->num_triangles < 0 || d->num_triangles > RT_MAX_TRIANGLES)
+    return fail(RT_ERR_INVALID_ARGUMENT, "num_triangles %lld out of range [0, %lld]", (long long)d->num_triangles,
+                (long long)RT_MAX_TRIANGLES);
+  if (d->num_spheres < 0 || d->num_spheres > (1 << 20))
+    return fail(RT_ERR_INVALID_ARGUMENT, "num_spheres %d out of range", d->num_spheres);
+  if (d->num_planes < 0 || d->num_planes > (1 << 16))
+    return fail(RT_ERR_INVALID_ARGUMENT, "num_planes %d out of range", d->num_planes);
+  if (d->num_materials < 1 || d->num_materials > RT_MAX_MATERIALS)
+    return fail(RT_ERR_INVALID_ARGUMENT, "num_materials %d out of range [1, %d]", d->num_materials, RT_MAX_MATERIALS);
+  if (d->num_lights < 0 || d->num_lights > RT_MAX_LIGHTS)
+    return fail(RT_ERR_INVALID_ARGUMENT, "num_lights %d out of range [0, %d]", d->num_lights, RT_MAX_LIGHTS);
+  if (d->flags & ~uint32_t(RT_ACCEL_NONE)) return fail(RT_ERR_INVALID_ARGUMENT, "unknown scene flags 0x%x", d->flags);
+  if (!finite3(d->ambient) || !finite3(d->background))
+    return fail(RT_ERR_INVALID_ARGUMENT, "ambient and background must be finite");
+  return RT_OK;
+}
+
+rt_status validate_camera(const rt_stereo_camera* c) {
+  if (!c) return fail(RT_ERR_INVALID_ARGUMENT, "camera is NULL");
+  if (!finite3(c->center) || !finite3(c->forward) || !finite3(c->up))
+    return fail(RT_ERR_INVALID_ARGUMENT, "camera vectors must be finite");
+  if (!(c->hfov_deg > 0.f && c->hfov_deg < 180.f))
+    return fail(RT_ERR_INVALID_ARGUMENT, "hfov_deg %g outside (0, 180)", double(c->hfov_deg));
+  if (!(std::isfinite(c->baseline) && c->baseline >= 0.f))
+    return fail(RT_ERR_INVALID_ARGUMENT, "baseline must be finite and >= 0");
+  if (!std::isfinite(c->convergence)) return fail(RT_ERR_INVALID_ARGUMENT, "convergence must be finite");
+  if (c->width < 1 || c->height < 1 || int64_t(c->width) * c->height > RT_MAX_PIXELS)
+    return fail(RT_ERR_INVALID_ARGUMENT, "image size %dx%d out of range", c->width, c->height);
+  if (c->max_depth < 0 || c->max_depth > RT_MAX_DEPTH)
+    return fail(RT_ERR_INVALID_ARGUMENT, "max_depth %d out of range [0, %d]", c->max_depth, RT_MAX_DEPTH);
+  double f[3] = {c->forward[0], c->forward[1], c->forward[2]}, u[3] = {c->up[0], c->up[1], c->up[2]};
+  double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  if (!(fl > 0.0)) return fail(RT_ERR_INVALID_ARGUMENT, "forward must be non-zero");
+  double cr[3] = {u[1] * f[2] - u[2] * f[1], u[2] * f[0] - u[0] * f[2], u[0] * f[1] - u[1] * f[0]};
+  double cl = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+  double ul = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  if (!(cl > 1e-12 * fl * ul)) return fail(RT_ERR_INVALID_ARGUMENT, "up must not be parallel to forward");
+  return RT_OK;
+}
+
+srt::DevCamera make_dev_camera(const rt_stereo_camera* c) {
+  srt::DevCamera d{};
+  double f[3], up[3];
+  for (int k = 0; k < 3; ++k) {
+    d.C[k] = c->center[k];
+    f[k] = c->forward[k];
+    up[k] = c->up[k];
+  }
+  double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  for (int k = 0; k < 3; ++k) d.f[k] = f[k] / fl;
+  double r[3] = {up[1] * d.f[2] - up[2] * d.f[1], up[2] * d.f[0] - up[0] * d.f[2], up[0] * d.f[1] - up[1] * d.f[0]};
+  double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  for (int k = 0; k < 3; ++k) d.r[k] = r[k] / rl;
+  d.u[0] = d.f[1] * d.r[2] - d.f[2] * d.r[1];
+  d.u[1] = d.f[2] * d.r[0] - d.f[0] * d.r[2];
+  d.u[2] = d.f[0] * d.r[1] - d.f[1] * d.r[0];
+  const double half = 0.5 * double(c->hfov_deg) * M_PI / 180.0;
+  d.fpx = 0.5 * double(c->width) / std::tan(half);
+  d.cx = 0.5 * double(c->width);
+  d.cy = 0.5 * double(c->height);
+  d.half_baseline = 0.5 * double(c->baseline);
+  d.inv_convergence = c->convergence > 0.f ? 1.0 / double(c->convergence) : 0.0;
+  d.W = c->width;
+  d.H = c->height;
+  d.D = c->max_depth;
+  d.tiles_x = (c->width + srt::kTile - 1) / srt::kTile;
+  d.tiles_y = (c->height + srt::kTile - 1) / srt::kTile;
+  return d;
+}
+
+int64_t total_paths(const rt_stereo_camera* c) {
+  int64_t tx = (c->width + srt::kTile - 1) / srt::kTile, ty = (c->height + srt::kTile - 1) / srt::kTile;
+  return tx * ty * srt::kPathsPerTile;
+}
+
+constexpr int64_t kMinChunk = 32 * srt::kPathsPerTile;
+constexpr int64_t kMaxChunk = int64_t(1) << 25;
+
+// Largest pass size (multiple of a tile pair) whose workspace fits `bytes`.
+int64_t chunk_for(int64_t total, int32_t L, size_t bytes, srt::RenderPlan* plan) {
+  int64_t hi_tiles = std::min(total, kMaxChunk) / srt::kPathsPerTile;
+  int64_t lo_tiles = std::min<int64_t>(kMinChunk / srt::kPathsPerTile, hi_tiles);
+  if (srt::plan_render(lo_tiles * srt::kPathsPerTile, L, 0, plan) > bytes) return 0;
+  while (lo_tiles < hi_tiles) {
+    int64_t mid = (lo_tiles + hi_tiles + 1) / 2;
+    if (srt::plan_render(mid * srt::kPathsPerTile, L, 0, plan) <= bytes)
+      lo_tiles = mid;
+    else
+      hi_tiles = mid - 1;
+  }
+  int64_t chunk = lo_tiles * srt::kPathsPerTile;
+  srt::plan_render(chunk, L, 0, plan);
+  return chunk;
+}
+
+bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+rt_status check_output(const rt_stereo_output* o, uint32_t flags) {
+  if (!o) return fail(RT_ERR_INVALID_ARGUMENT, "output is NULL");
+  if (!o->radiance[0] || !o->radiance[1]) return fail(RT_ERR_INVALID_ARGUMENT, "radiance outputs are required");
+  if ((flags & RT_FLAG_PATH_IDS) &&
+      !(o->path_prims[0] && o->path_prims[1] && o->shadow_state[0] && o->shadow_state[1]))
+    return fail(RT_ERR_INVALID_ARGUMENT, "RT_FLAG_PATH_IDS needs path_prims and shadow_state for both eyes");
+  if (!!o->host_radiance[0] != !!o->host_radiance[1])
+    return fail(RT_ERR_INVALID_ARGUMENT, "host_radiance must be given for both eyes or neither");
+  return RT_OK;
+}
+
+constexpr uint32_t kKnownFlags = RT_FLAG_PATH_IDS | RT_FLAG_COUNT_WORK | RT_FLAG_BRUTE_FORCE;
+
+rt_status render_one(const rt_scene_s* scene, const rt_stereo_camera* cam, const rt_stereo_output* out, char* ws,
+                     size_t ws_bytes, uint32_t flags, hipStream_t stream, hipStream_t copy_stream,
+                     srt::TimerImpl* timer) {
+  const int64_t total = total_paths(cam);
+  srt::RenderPlan plan;
+  const int64_t chunk = chunk_for(total, scene->dev.L, ws_bytes, &plan);
+  if (chunk == 0) {
+    size_t need = 0;
+    rt_render_workspace_min(scene->dev.L, &need);
+    return fail(RT_ERR_BUFFER_TOO_SMALL, "workspace of %zu bytes is below the minimum of %zu bytes", ws_bytes, need);
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != scene->device)
+    return fail(RT_ERR_INVALID_ARGUMENT, "scene was built on device %d, current device is %d", scene->device, dev);
+  plan.grid_trace = srt::trace_grid_size(dev);
+  srt::RenderArgs ra;
+  ra.scene = scene->dev;
+  ra.cam = make_dev_camera(cam);
+  ra.out = out;
+  ra.flags = flags;
+  ra.ws = ws;
+  ra.plan = plan;
+  for (int64_t begin = 0; begin < total; begin += chunk) {
+    ra.path_begin = begin;
+    ra.path_count = std::min(chunk, total - begin);
+    e = srt::render_chunk(ra, stream, timer);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  if (out->host_radiance[0]) {
+    const size_t bytes = size_t(cam->width) * size_t(cam->height) * 12;
+    hipStream_t cs = copy_stream ? copy_stream : stream;
+    if (cs != stream) {
+      hipEvent_t ev;
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+      e = hipEventRecord(ev, stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
+      (void)hipEventDestroy(ev);
+      if (e != hipSuccess) return hip_fail(e, "stream ordering for readback");
+    }
+    if (timer) srt::timer_begin(timer, RT_STAGE_READBACK, cs);
+    for (int eye = 0; eye < 2 && e == hipSuccess; ++eye)
+      e = hipMemcpyAsync(out->host_radiance[eye], out->radiance[eye], bytes, hipMemcpyDeviceToHost, cs);
+    if (timer) srt::timer_end(timer, RT_STAGE_READBACK, cs);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (readback)");
+  }
+  return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rt_last_error(void) { return g_error.c_str(); }
+
+int32_t rt_version(void) { return 100; }
+
+rt_status rt_scene_storage_size(const rt_scene_desc* desc, size_t* storage_bytes, size_t* scratch_bytes) {
+  rt_status s = validate_desc(desc);
+  if (s != RT_OK) return s;
+  if (!storage_bytes || !scratch_bytes) return fail(RT_ERR_INVALID_ARGUMENT, "size outputs are NULL");
+  srt::BuildPlan p = srt::plan_build(desc->num_triangles, desc->num_spheres, desc->num_planes, desc->num_materials,
+                                     desc->num_lights, desc->flags == RT_ACCEL_LBVH);
+  *storage_bytes = p.storage_bytes;
+  *scratch_bytes = p.scratch_bytes;
+  return ok();
+}
+
+rt_status rt_scene_build(const rt_scene_desc* desc, void* storage, size_t storage_bytes, void* scratch,
+                         size_t scratch_bytes, void* stream, rt_scene* out) {
+  rt_status s = validate_desc(desc);
+  if (s != RT_OK) return s;
+  if (!out) return fail(RT_ERR_INVALID_ARGUMENT, "output handle pointer is NULL");
+  *out = nullptr;
+  if ((desc->num_triangles > 0 && (!desc->triangles || !desc->tri_material)) ||
+      (desc->num_spheres > 0 && (!desc->spheres || !desc->sphere_material)) ||
+      (desc->num_planes > 0 && (!desc->planes || !desc->plane_material)) || !desc->materials ||
+      (desc->num_lights > 0 && !desc->lights))
+    return fail(RT_ERR_INVALID_ARGUMENT, "an array with a non-zero count is NULL");
+  for (int i = 0; i < desc->num_materials; ++i) {
+    const rt_material& m = desc->materials[i];
+    if (!finite3(m.albedo) || !finite3(m.specular) || !finite3(m.reflectance) || !std::isfinite(m.shininess) ||
+        !(m.shininess > 0.f))
+      return fail(RT_ERR_INVALID_ARGUMENT, "material %d has a non-finite value or shininess <= 0", i);
+  }
+  for (int i = 0; i < desc->num_lights; ++i)
+    if (!finite3(desc->lights[i].position) || !finite3(desc->lights[i].intensity))
+      return fail(RT_ERR_INVALID_ARGUMENT, "light %d is not finite", i);
+  srt::BuildPlan plan = srt::plan_build(desc->num_triangles, desc->num_spheres, desc->num_planes, desc->num_materials,
+                                        desc->num_lights, desc->flags == RT_ACCEL_LBVH);
+  if (!storage || !scratch) return fail(RT_ERR_INVALID_ARGUMENT, "storage and scratch must be device pointers");
+  if (!aligned256(storage) || !aligned256(scratch))
+    return fail(RT_ERR_INVALID_ARGUMENT, "storage and scratch must be 256-byte aligned");
+  if (storage_bytes < plan.storage_bytes)
+    return fail(RT_ERR_BUFFER_TOO_SMALL, "storage of %zu bytes, %zu required", storage_bytes, plan.storage_bytes);
+  if (scratch_bytes < plan.scratch_bytes)
+    return fail(RT_ERR_BUFFER_TOO_SMALL, "scratch of %zu bytes, %zu required", scratch_bytes, plan.scratch_bytes);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  srt::BuildResult res{};
+  char* st = static_cast<char*>(storage);
+  e = srt::build_scene_device(desc, plan, st, static_cast<char*>(scratch), static_cast<hipStream_t>(stream), &res);
+  if (e != hipSuccess) return hip_fail(e, "scene build");
+  if (res.status_bits & 1u) return fail(RT_ERR_INVALID_ARGUMENT, "a triangle vertex is not finite");
+  if (res.status_bits & 2u) return fail(RT_ERR_INVALID_ARGUMENT, "a triangle material index is out of range");
+  if (res.status_bits & 4u)
+    return fail(RT_ERR_INVALID_ARGUMENT, "a sphere is not finite, has radius <= 0 or a material out of range");
+  if (res.status_bits & 8u)
+    return fail(RT_ERR_INVALID_ARGUMENT, "a plane is not finite, has a zero normal or a material out of range");
+  if (res.status_bits & 16u) return fail(RT_ERR_DEVICE, "internal error: inconsistent BVH hierarchy");
+  if (res.depth > 96) return fail(RT_ERR_UNSUPPORTED, "BVH depth %d exceeds the traversal stack", res.depth);
+
+  rt_scene_s* h = new (std::nothrow) rt_scene_s();
+  if (!h) return fail(RT_ERR_DEVICE, "out of host memory");
+  srt::DevScene& d = h->dev;
+  d.nodes = reinterpret_cast<const float4*>(st + plan.nodes_off);
+  d.tris = reinterpret_cast<const float4*>(st + plan.tris_off);
+  d.spheres = reinterpret_cast<const float4*>(st + plan.spheres_off);
+  d.sphere_mat = reinterpret_cast<const uint32_t*>(st + plan.sphere_mat_off);
+  d.planes = reinterpret_cast<const float4*>(st + plan.planes_off);
+  d.plane_mat = reinterpret_cast<const uint32_t*>(st + plan.plane_mat_off);
+  d.materials = reinterpret_cast<const float4*>(st + plan.mats_off);
+  d.lights = reinterpret_cast<const float4*>(st + plan.lights_off);
+  d.T = int32_t(desc->num_triangles);
+  d.S = desc->num_spheres;
+  d.P = desc->num_planes;
+  d.L = desc->num_lights;
+  d.M = desc->num_materials;
+  d.root = res.root;
+  d.num_nodes = int32_t(res.num_nodes);
+  d.has_bvh = plan.bvh ? 1 : 0;
+  for (int k = 0; k < 3; ++k) {
+    d.ambient[k] = desc->ambient[k];
+    d.background[k] = desc->background[k];
+  }
+  h->device = dev;
+  rt_scene_info& info = h->info;
+  info.num_triangles = desc->num_triangles;
+  info.num_spheres = desc->num_spheres;
+  info.num_planes = desc->num_planes;
+  info.num_lights = desc->num_lights;
+  info.num_materials = desc->num_materials;
+  info.bvh_depth = plan.bvh ? res.depth : 0;
+  info.leaf_size = desc->num_triangles > 0 ? 1 : 0;
+  info.num_nodes = res.num_nodes;
+  info.node_bytes = res.num_nodes * 64;
+  info.triangle_bytes = desc->num_triangles * 48;
+  for (int k = 0; k < 3; ++k) {
+    info.bounds_lo[k] = res.lo[k];
+    info.bounds_hi[k] = res.hi[k];
+  }
+  *out = h;
+  return ok();
+}
+
+rt_status rt_scene_release(rt_scene scene) {
+  if (!scene) return fail(RT_ERR_INVALID_ARGUMENT, "scene is NULL");
+  delete scene;
+  return ok();
+}
+
+rt_status rt_scene_get_info(rt_scene scene, rt_scene_info* info) {
+  if (!scene || !info) return fail(RT_ERR_INVALID_ARGUMENT, "scene or info is NULL");
+  *info = scene->info;
+  return ok();
+}
+
+rt_status rt_render_workspace_size(const rt_stereo_camera* camera, int32_t num_lights, size_t* bytes) {
+  rt_status s = validate_camera(camera);
+  if (s != RT_OK) return s;
+  if (num_lights < 0 || num_lights > RT_MAX_LIGHTS || !bytes)
+    return fail(RT_ERR_INVALID_ARGUMENT, "num_lights out of range or bytes is NULL");
+  srt::RenderPlan plan;
+  *bytes = srt::plan_render(std::min(total_paths(camera), kMaxChunk), num_lights, 0, &plan);
+  return ok();
+}
+
+rt_status rt_render_workspace_min(int32_t num_lights, size_t* bytes) {
+  if (num_lights < 0 || num_lights > RT_MAX_LIGHTS || !bytes)
+    return fail(RT_ERR_INVALID_ARGUMENT, "num_lights out of range or bytes is NULL");
+  srt::RenderPlan plan;
+  *bytes = srt::plan_render(kMinChunk, num_lights, 0, &plan);
+  return ok();
+}
+
+rt_status rt_render_stereo(rt_scene scene, const rt_stereo_camera* camera, const rt_stereo_output* out,
+                           void* workspace, size_t workspace_bytes, uint32_t flags, void* stream, void* copy_stream,
+                           rt_timer timer) {
+  if (!scene) return fail(RT_ERR_INVALID_ARGUMENT, "scene is NULL");
+  rt_status s = validate_camera(camera);
+  if (s != RT_OK) return s;
+  if ((s = check_output(out, flags)) != RT_OK) return s;
+  if (flags & ~kKnownFlags) return fail(RT_ERR_INVALID_ARGUMENT, "unknown render flags 0x%x", flags);
+  if (!workspace || !aligned256(workspace))
+    return fail(RT_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");
+  s = render_one(scene, camera, out, static_cast<char*>(workspace), workspace_bytes, flags,
+                 static_cast<hipStream_t>(stream), static_cast<hipStream_t>(copy_stream), timer);
+  if (s != RT_OK) return s;
+  if (timer && timer->error != hipSuccess) return hip_fail(timer->error, "timer event");
+  return ok();
+}
+
+rt_status rt_render_batch_workspace_size(const rt_batch_item* items, int32_t n, size_t* bytes) {
+  if (n < 0 || (n > 0 && !items) || !bytes) return fail(RT_ERR_INVALID_ARGUMENT, "bad batch arguments");
+  size_t best = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!items[i].scene) return fail(RT_ERR_INVALID_ARGUMENT, "item %d has no scene", i);
+    size_t b = 0;
+    rt_status s = rt_render_workspace_size(&items[i].camera, items[i].scene->dev.L, &b);
+    if (s != RT_OK) return s;
+    best = std::max(best, b);
+  }
+  *bytes = best;
+  return ok();
+}
+
+rt_status rt_render_batch(const rt_batch_item* items, int32_t n, void* workspace, size_t workspace_bytes,
+                          uint32_t flags, void* stream, rt_timer timer) {
+  if (n < 0 || (n > 0 && !items)) return fail(RT_ERR_INVALID_ARGUMENT, "bad batch arguments");
+  if (flags & ~kKnownFlags) return fail(RT_ERR_INVALID_ARGUMENT, "unknown render flags 0x%x", flags);
+  if (!workspace || !aligned256(workspace))
+    return fail(RT_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");
+  for (int i = 0; i < n; ++i) {
+    if (!items[i].scene) return fail(RT_ERR_INVALID_ARGUMENT, "item %d has no scene", i);
+    rt_status s = validate_camera(&items[i].camera);
+    if (s != RT_OK) return s;
+    if ((s = check_output(&items[i].out, flags)) != RT_OK) return s;
+  }
+  for (int i = 0; i < n; ++i) {
+    rt_status s = render_one(items[i].scene, &items[i].camera, &items[i].out, static_cast<char*>(workspace),
+                             workspace_bytes, flags, static_cast<hipStream_t>(stream), nullptr, timer);
+    if (s != RT_OK) return s;
+  }
+  return ok();
+}
+
+rt_status rt_timer_create(rt_timer* out) {
+  if (!out) return fail(RT_ERR_INVALID_ARGUMENT, "timer pointer is NULL");
+  *out = new (std::nothrow) rt_timer_s();
+  if (!*out) return fail(RT_ERR_DEVICE, "out of host memory");
+  return ok();
+}
+
+rt_status rt_timer_destroy(rt_timer timer) {
+  if (!timer) return fail(RT_ERR_INVALID_ARGUMENT, "timer is NULL");
+  for (auto& r : timer->recs) {
+    (void)hipEventSynchronize(r.end);
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.end);
+  }
+  for (hipEvent_t e : timer->pool) (void)hipEventDestroy(e);
+  if (timer->pending_start) (void)hipEventDestroy(timer->pending_start);
+  delete timer;
+  return ok();
+}
+
+rt_status rt_timer_read(rt_timer timer, rt_timing* out) {
+  if (!timer || !out) return fail(RT_ERR_INVALID_ARGUMENT, "timer or output is NULL");
+  hipError_t err = hipSuccess;
+  for (auto& r : timer->recs) {
+    hipError_t e = hipEventSynchronize(r.end);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.end);
+    if (e != hipSuccess && err == hipSuccess) err = e;
+    if (r.stage >= 0 && r.stage < RT_NUM_STAGES) {
+      out->ms[r.stage] += double(ms);
+      out->launches[r.stage] += 1;
+    }
+    timer->pool.push_back(r.start);
+    timer->pool.push_back(r.end);
+  }
+  timer->recs.clear();
+  if (err != hipSuccess) return hip_fail(err, "timer read");
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,675 @@
+// Linear BVH build on the device (gfx950).
+//
+// The paper (Section 3, Table 1) lists BVH trees as fast to construct, simple to
+// traverse and well suited to GPUs.  The tree here is a linear BVH:
+//   1. per triangle: bounding box and centroid, input validation;
+//   2. reduction of the centroid and scene bounds;
+//   3. 63-bit Morton code of the centroid quantised to 2^21 cells per axis;
+//   4. stable LSD radix sort of (code, triangle id), 8 passes of 8 bits;
+//   5. Karras (2012) emission of the T-1 internal nodes from the sorted codes
+//      (split at the highest differing bit; equal codes split by index);
+//   6. bottom-up box refit (an atomic arrival counter per node, the second
+//      child to arrive unions both boxes and climbs on);
+//   7. packing into 64-byte BVH2 nodes that carry both children's boxes, and
+//      48-byte triangle records in leaf order.
+// No SAH.  Every step is deterministic, so a scene always builds the same tree.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+#include "rt_internal.h"
+
+namespace srt {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kSortItems = 16;                      // keys per thread per sort tile
+constexpr int kSortTile = kBlock * kSortItems;      // 4096 keys per block
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+__device__ inline bool finite3(float a, float b, float c) {
+  return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+// ---------------------------------------------------------------------------------------------
+// 1-2. Triangle boxes, validation, bounds
+// ---------------------------------------------------------------------------------------------
+
+struct Bounds6 {
+  float clo[3], chi[3];  // centroid bounds
+  float blo[3], bhi[3];  // scene box
+};
+
+__global__ __launch_bounds__(kBlock) void k_tri_prep(const float* __restrict__ tris,
+                                                     const uint32_t* __restrict__ mat, int64_t T, int32_t M,
+                                                     float4* __restrict__ lo_out, float4* __restrict__ hi_out,
+                                                     Bounds6* __restrict__ partial, uint32_t* __restrict__ status) {
+  __shared__ float red[12][kBlock];
+  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  float c[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (i < T) {
+    const float* p = tris + 9 * i;
+    float v[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] = p[k];
+    bool ok = finite3(v[0], v[1], v[2]) && finite3(v[3], v[4], v[5]) && finite3(v[6], v[7], v[8]);
+    if (!ok) atomicOr(status, 1u);
+    if (mat[i] >= uint32_t(M)) atomicOr(status, 2u);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(v[a], fminf(v[3 + a], v[6 + a]));
+      hi[a] = fmaxf(v[a], fmaxf(v[3 + a], v[6 + a]));
+      c[a] = 0.5f * lo[a] + 0.5f * hi[a];
+      cmax[a] = c[a];
+    }
+    lo_out[i] = make_float4(lo[0], lo[1], lo[2], 0.f);
+    hi_out[i] = make_float4(hi[0], hi[1], hi[2], 0.f);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    red[a][threadIdx.x] = c[a];
+    red[3 + a][threadIdx.x] = cmax[a];
+    red[6 + a][threadIdx.x] = lo[a];
+    red[9 + a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = fminf(red[a][threadIdx.x], red[a][threadIdx.x + s]);
+        red[3 + a][threadIdx.x] = fmaxf(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + s]);
+        red[6 + a][threadIdx.x] = fminf(red[6 + a][threadIdx.x], red[6 + a][threadIdx.x + s]);
+        red[9 + a][threadIdx.x] = fmaxf(red[9 + a][threadIdx.x], red[9 + a][threadIdx.x + s]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    Bounds6 b;
+    for (int a = 0; a < 3; ++a) {
+      b.clo[a] = red[a][0];
+      b.chi[a] = red[3 + a][0];
+      b.blo[a] = red[6 + a][0];
+      b.bhi[a] = red[9 + a][0];
+    }
+    partial[blockIdx.x] = b;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_bounds(Bounds6* __restrict__ partial, int64_t n) {
+  __shared__ float red[12][kBlock];
+  float v[12];
+  for (int a = 0; a < 3; ++a) {
+    v[a] = INFINITY;
+    v[3 + a] = -INFINITY;
+    v[6 + a] = INFINITY;
+    v[9 + a] = -INFINITY;
+  }
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    Bounds6 b = partial[i];
+    for (int a = 0; a < 3; ++a) {
+      v[a] = fminf(v[a], b.clo[a]);
+      v[3 + a] = fmaxf(v[3 + a], b.chi[a]);
+      v[6 + a] = fminf(v[6 + a], b.blo[a]);
+      v[9 + a] = fmaxf(v[9 + a], b.bhi[a]);
+    }
+  }
+  for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = fminf(red[a][threadIdx.x], red[a][threadIdx.x + s]);
+        red[3 + a][threadIdx.x] = fmaxf(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + s]);
+        red[6 + a][threadIdx.x] = fminf(red[6 + a][threadIdx.x], red[6 + a][threadIdx.x + s]);
+        red[9 + a][threadIdx.x] = fmaxf(red[9 + a][threadIdx.x], red[9 + a][threadIdx.x + s]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    Bounds6 b;
+    for (int a = 0; a < 3; ++a) {
+      b.clo[a] = red[a][0];
+      b.chi[a] = red[3 + a][0];
+      b.blo[a] = red[6 + a][0];
+      b.bhi[a] = red[9 + a][0];
+    }
+    partial[0] = b;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_spheres_planes(const float* __restrict__ spheres,
+                                                                 const uint32_t* __restrict__ smat, int32_t S,
+                                                                 const float* __restrict__ planes,
+                                                                 const uint32_t* __restrict__ pmat, int32_t P,
+                                                                 int32_t M, uint32_t* __restrict__ status) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < S) {
+    const float* s = spheres + 4 * i;
+    if (!(finite3(s[0], s[1], s[2]) && isfinite(s[3]) && s[3] > 0.f) || smat[i] >= uint32_t(M)) atomicOr(status, 4u);
+  } else if (i < S + P) {
+    int k = i - S;
+    const float* p = planes + 4 * k;
+    bool ok = finite3(p[0], p[1], p[2]) && isfinite(p[3]) && (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) > 0.f;
+    if (!ok || pmat[k] >= uint32_t(M)) atomicOr(status, 8u);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// 3. Morton codes
+// ---------------------------------------------------------------------------------------------
+
+__device__ inline uint64_t spread21(uint32_t x) {
+  uint64_t v = x & 0x1fffffu;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_morton(const float4* __restrict__ lo, const float4* __restrict__ hi,
+                                                   const Bounds6* __restrict__ bounds, int64_t T,
+                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ ids) {
+  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= T) return;
+  Bounds6 b = bounds[0];
+  float4 l = lo[i], h = hi[i];
+  float c[3] = {0.5f * l.x + 0.5f * h.x, 0.5f * l.y + 0.5f * h.y, 0.5f * l.z + 0.5f * h.z};
+  uint32_t q[3];
+  const float cells = 2097152.0f;  // 2^21
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float ext = b.chi[a] - b.clo[a];
+    float s = ext > 0.f ? (c[a] - b.clo[a]) / ext * cells : 0.f;
+    s = fminf(fmaxf(s, 0.f), cells - 1.f);
+    q[a] = uint32_t(s);
+  }
+  keys[i] = (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
+  ids[i] = uint32_t(i);
+}
+
+// ---------------------------------------------------------------------------------------------
+// 4. Stable LSD radix sort, 8 bits per pass
+// ---------------------------------------------------------------------------------------------
+
+// Per-block digit histogram, stored digit-major: hist[digit * nblocks + block].
+__global__ __launch_bounds__(kBlock) void k_digit_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                       uint32_t* __restrict__ hist, int64_t nblocks) {
+  __shared__ uint32_t h[kRadix];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = int64_t(blockIdx.x) * kSortTile;
+#pragma unroll 4
+  for (int k = 0; k < kSortItems; ++k) {
+    int64_t i = base + int64_t(k) * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
+  hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of hist (length m) in place, one block.
+__global__ __launch_bounds__(1024) void k_scan_exclusive(uint32_t* __restrict__ data, int64_t m) {
+  __shared__ uint32_t part[1024];
+  const int tid = threadIdx.x;
+  int64_t per = (m + 1023) / 1024;
+  int64_t begin = tid * per, end = begin + per < m ? begin + per : m;
+  uint32_t s = 0;
+  for (int64_t i = begin; i < end; ++i) s += data[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = tid >= off ? part[tid - off] : 0u;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[tid] - s;
+  for (int64_t i = begin; i < end; ++i) {
+    uint32_t x = data[i];
+    data[i] = run;
+    run += x;
+  }
+}
+
+__device__ inline uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Stable scatter: element order inside the tile is (round, thread), i.e. index order.
+__global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t* __restrict__ keys_in,
+                                                    const uint32_t* __restrict__ ids_in, int64_t n, int shift,
+                                                    const uint32_t* __restrict__ offsets, int64_t nblocks,
+                                                    uint64_t* __restrict__ keys_out, uint32_t* __restrict__ ids_out) {
+  __shared__ uint32_t running[kRadix];
+  __shared__ uint32_t wave_cnt[kBlock / 64][kRadix];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  running[tid] = offsets[int64_t(tid) * nblocks + blockIdx.x];
+  for (int w = 0; w < kBlock / 64; ++w) wave_cnt[w][tid] = 0;
+  __syncthreads();
+  int64_t base = int64_t(blockIdx.x) * kSortTile;
+  for (int k = 0; k < kSortItems; ++k) {
+    int64_t i = base + int64_t(k) * kBlock + tid;
+    bool valid = i < n;
+    uint64_t key = valid ? keys_in[i] : 0;
+    uint32_t id = valid ? ids_in[i] : 0;
+    uint32_t digit = uint32_t((key >> shift) & (kRadix - 1));
+    // lanes of this wave holding the same digit
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      uint64_t bal = __ballot((digit >> b) & 1u);
+      peers &= ((digit >> b) & 1u) ? bal : ~bal;
+    }
+    uint32_t rank = __popcll(peers & lanemask_lt());
+    bool leader = valid && rank == 0;
+    if (leader) wave_cnt[wave][digit] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = running[digit] + rank;
+      for (int w = 0; w < wave; ++w) pos += wave_cnt[w][digit];
+      if (pos < uint64_t(n)) {
+        keys_out[pos] = key;
+        ids_out[pos] = id;
+      }
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      add += wave_cnt[w][tid];
+      wave_cnt[w][tid] = 0;
+    }
+    running[tid] += add;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// 5. Karras (2012) hierarchy emission
+// ---------------------------------------------------------------------------------------------
+
+__device__ inline int delta(const uint64_t* __restrict__ k, int64_t n, int64_t i, int64_t j) {
+  if (j < 0 || j >= n) return -1;
+  uint64_t a = k[i], b = k[j];
+  if (a != b) return __clzll(a ^ b);
+  return 64 + __clz(uint32_t(i) ^ uint32_t(j));
+}
+
+// children[i] = (left, right) references, parents of internal nodes at parent[0..T-2],
+// parents of leaves at parent[T-1 + leaf]; range[i] = (first, last) sorted leaf indices.
+__global__ __launch_bounds__(kBlock) void k_karras(const uint64_t* __restrict__ keys, int64_t n,
+                                                   int2* __restrict__ children, int32_t* __restrict__ parent,
+                                                   int2* __restrict__ range) {
+  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n - 1) return;
+  int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+  int dmin = delta(keys, n, i, i - d);
+  int64_t lmax = 2;
+  while (delta(keys, n, i, i + lmax * d) > dmin) lmax *= 2;
+  int64_t l = 0;
+  for (int64_t t = lmax / 2; t >= 1; t /= 2)
+    if (delta(keys, n, i, i + (l + t) * d) > dmin) l += t;
+  int64_t j = i + l * d;
+  int dnode = delta(keys, n, i, j);
+  int64_t s = 0, t = l;
+  do {
+    t = (t + 1) >> 1;
+    if (delta(keys, n, i, i + (s + t) * d) > dnode) s += t;
+  } while (t > 1);
+  int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
+  int64_t first = i < j ? i : j, last = i < j ? j : i;
+  int left = (first == gamma) ? ~int(gamma) : int(gamma);           // leaf refs as ~index here
+  int right = (last == gamma + 1) ? ~int(gamma + 1) : int(gamma + 1);
+  children[i] = make_int2(left, right);
+  range[i] = make_int2(int(first), int(last));
+  if (gamma < 0 || gamma + 1 >= n) return;  // cannot happen for a valid split; never write out of bounds
+  if (left < 0) parent[n - 1 + ~left] = int(i); else parent[left] = int(i);
+  if (right < 0) parent[n - 1 + ~right] = int(i); else parent[right] = int(i);
+}
+
+// ---------------------------------------------------------------------------------------------
+// 6. Bottom-up refit
+// ---------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_refit(const int2* __restrict__ children,
+                                                  const int32_t* __restrict__ parent,
+                                                  const float4* __restrict__ leaf_lo, const float4* __restrict__ leaf_hi,
+                                                  const uint32_t* __restrict__ sorted_ids, float4* nodebox,
+                                                  uint32_t* flags, int64_t n, int32_t* __restrict__ max_depth,
+                                                  uint32_t* __restrict__ status) {
+  int64_t leaf = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (leaf >= n) return;
+  int node = parent[n - 1 + leaf];
+  int depth = 1;
+  for (int guard = 0; guard < 256; ++guard) {
+    if (node < 0 || node >= n - 1) {  // corrupt parent link: report instead of reading out of bounds
+      atomicOr(status, 16u);
+      return;
+    }
+    uint32_t old = __hip_atomic_fetch_add(&flags[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 0) break;  // the sibling subtree is still being built; its thread climbs on
+    int2 ch = children[node];
+    float4 lo[2], hi[2];
+    int c[2] = {ch.x, ch.y};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (c[k] < 0) {
+        uint32_t id = sorted_ids[~c[k]];
+        lo[k] = leaf_lo[id];
+        hi[k] = leaf_hi[id];
+      } else {
+        lo[k] = nodebox[2 * c[k]];
+        hi[k] = nodebox[2 * c[k] + 1];
+      }
+    }
+    nodebox[2 * node] = make_float4(fminf(lo[0].x, lo[1].x), fminf(lo[0].y, lo[1].y), fminf(lo[0].z, lo[1].z), 0.f);
+    nodebox[2 * node + 1] =
+        make_float4(fmaxf(hi[0].x, hi[1].x), fmaxf(hi[0].y, hi[1].y), fmaxf(hi[0].z, hi[1].z), 0.f);
+    if (node == 0) break;
+    node = parent[node];
+  }
+  // depth of this leaf: count ancestors (read-only walk over the parent links)
+  int nd = parent[n - 1 + leaf];
+  while (nd != 0 && depth < 256) {
+    nd = parent[nd];
+    if (nd < 0 || nd >= n - 1) {
+      atomicOr(status, 16u);
+      return;
+    }
+    ++depth;
+  }
+  atomicMax(max_depth, depth);
+}
+
+// ---------------------------------------------------------------------------------------------
+// 7. Packing
+// ---------------------------------------------------------------------------------------------
+
+struct PackArgs {
+  const int2* children;
+  const int2* range;
+  const float4* leaf_lo;
+  const float4* leaf_hi;
+  const uint32_t* sorted_ids;
+  const float4* nodebox;
+  float4* nodes;
+  int64_t n;
+  float pad;
+  int leaf_size;
+};
+
+__device__ inline void child_box(const PackArgs& a, int ref, float4* lo, float4* hi) {
+  if (ref < 0) {
+    uint32_t id = a.sorted_ids[~ref];
+    *lo = a.leaf_lo[id];
+    *hi = a.leaf_hi[id];
+  } else {
+    *lo = a.nodebox[2 * ref];
+    *hi = a.nodebox[2 * ref + 1];
+  }
+}
+
+// Reference to emit for a Karras child: subtrees of at most leaf_size triangles become one leaf.
+__device__ inline int child_ref(const PackArgs& a, int ref) {
+  if (ref < 0) return ~((~ref) << 2);
+  int2 r = a.range[ref];
+  int count = r.y - r.x + 1;
+  if (count <= a.leaf_size) return ~((r.x << 2) | (count - 1));
+  return ref;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_nodes(PackArgs a) {
+  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= a.n - 1) return;
+  int2 ch = a.children[i];
+  float4 l0, h0, l1, h1;
+  child_box(a, ch.x, &l0, &h0);
+  child_box(a, ch.y, &l1, &h1);
+  const float p = a.pad;
+  float4* out = a.nodes + 4 * i;
+  out[0] = make_float4(l0.x - p, h0.x + p, l0.y - p, h0.y + p);
+  out[1] = make_float4(l1.x - p, h1.x + p, l1.y - p, h1.y + p);
+  out[2] = make_float4(l0.z - p, h0.z + p, l1.z - p, h1.z + p);
+  out[3] = make_float4(__int_as_float(child_ref(a, ch.x)), __int_as_float(child_ref(a, ch.y)), 0.f, 0.f);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_tris(const float* __restrict__ tris, const uint32_t* __restrict__ mat,
+                                                      const uint32_t* __restrict__ order, int64_t T,
+                                                      float4* __restrict__ recs) {
+  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= T) return;
+  uint32_t id = order ? order[i] : uint32_t(i);
+  const float* p = tris + 9 * int64_t(id);
+  float v0x = p[0], v0y = p[1], v0z = p[2];
+  recs[3 * i + 0] = make_float4(v0x, v0y, v0z, __int_as_float(int(id)));
+  recs[3 * i + 1] = make_float4(p[3] - v0x, p[4] - v0y, p[5] - v0z, __int_as_float(int(mat[id])));
+  recs[3 * i + 2] = make_float4(p[6] - v0x, p[7] - v0y, p[8] - v0z, 0.f);
+}
+
+template <typename T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline unsigned blocks_for(int64_t n, int b = kBlock) { return unsigned((n + b - 1) / b); }
+
+}  // namespace
+
+BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool bvh) {
+  BuildPlan p{};
+  p.T = T;
+  p.bvh = bvh && T >= 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  int64_t num_nodes = p.bvh ? T - 1 : 0;
+  p.nodes_off = take(size_t(num_nodes) * 64);
+  p.tris_off = take(size_t(T) * 48);
+  p.spheres_off = take(size_t(S) * 16);
+  p.sphere_mat_off = take(size_t(S) * 4);
+  p.planes_off = take(size_t(P) * 16);
+  p.plane_mat_off = take(size_t(P) * 4);
+  p.mats_off = take(size_t(M) * 48);
+  p.lights_off = take(size_t(L) * 32 + 32);
+  p.storage_bytes = off;
+
+  off = 0;
+  p.num_blocks_prep = (T + kBlock - 1) / kBlock;
+  p.num_sort_blocks = (T + kSortTile - 1) / kSortTile;
+  p.status_off = take(64);
+  p.partial_off = take(size_t(p.num_blocks_prep > 0 ? p.num_blocks_prep : 1) * sizeof(Bounds6));
+  if (T > 0) {
+    p.lo_off = take(size_t(T) * 16);
+    p.hi_off = take(size_t(T) * 16);
+  }
+  if (p.bvh) {
+    p.keys0_off = take(size_t(T) * 8);
+    p.keys1_off = take(size_t(T) * 8);
+    p.ids0_off = take(size_t(T) * 4);
+    p.ids1_off = take(size_t(T) * 4);
+    p.hist_off = take(size_t(p.num_sort_blocks) * kRadix * 4);
+    p.children_off = take(size_t(T) * 8);
+    p.range_off = take(size_t(T) * 8);
+    p.parent_off = take(size_t(2 * T) * 4);
+    p.flags_off = take(size_t(T) * 4);
+    p.nodebox_off = take(size_t(T) * 32);
+  }
+  p.scratch_bytes = off;
+  return p;
+}
+
+hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, char* storage, char* scratch,
+                              hipStream_t stream, BuildResult* result) {
+  const int64_t T = desc->num_triangles;
+  const int S = desc->num_spheres, P = desc->num_planes, M = desc->num_materials, L = desc->num_lights;
+  uint32_t* status = reinterpret_cast<uint32_t*>(scratch + plan.status_off);
+  hipError_t e;
+#define SRT_CHECK(x)                   \
+  do {                                 \
+    e = (x);                           \
+    if (e != hipSuccess) return e;     \
+  } while (0)
+#define SRT_LAUNCH_CHECK() SRT_CHECK(hipGetLastError())
+
+  k_fill<uint32_t><<<1, 64, 0, stream>>>(status, 0u, 16);
+  SRT_LAUNCH_CHECK();
+
+  // spheres, planes, materials, lights
+  if (S > 0) {
+    SRT_CHECK(hipMemcpyAsync(storage + plan.spheres_off, desc->spheres, size_t(S) * 16, hipMemcpyDeviceToDevice, stream));
+    SRT_CHECK(hipMemcpyAsync(storage + plan.sphere_mat_off, desc->sphere_material, size_t(S) * 4,
+                             hipMemcpyDeviceToDevice, stream));
+  }
+  if (P > 0) {
+    SRT_CHECK(hipMemcpyAsync(storage + plan.planes_off, desc->planes, size_t(P) * 16, hipMemcpyDeviceToDevice, stream));
+    SRT_CHECK(hipMemcpyAsync(storage + plan.plane_mat_off, desc->plane_material, size_t(P) * 4,
+                             hipMemcpyDeviceToDevice, stream));
+  }
+  if (S + P > 0) {
+    k_check_spheres_planes<<<blocks_for(S + P), kBlock, 0, stream>>>(desc->spheres, desc->sphere_material, S,
+                                                                     desc->planes, desc->plane_material, P, M, status);
+    SRT_LAUNCH_CHECK();
+  }
+  {
+    // materials: (kd, n), (ks, 0), (kr, 0); lights: (pos, 0), (I, 0)
+    size_t mb = size_t(M) * 48, lb = size_t(L) * 32;
+    float* host = static_cast<float*>(std::malloc(mb + lb + 16));
+    if (!host) return hipErrorOutOfMemory;
+    for (int i = 0; i < M; ++i) {
+      const rt_material& m = desc->materials[i];
+      float* o = host + 12 * i;
+      o[0] = m.albedo[0], o[1] = m.albedo[1], o[2] = m.albedo[2], o[3] = m.shininess;
+      o[4] = m.specular[0], o[5] = m.specular[1], o[6] = m.specular[2], o[7] = 0.f;
+      o[8] = m.reflectance[0], o[9] = m.reflectance[1], o[10] = m.reflectance[2], o[11] = 0.f;
+    }
+    for (int i = 0; i < L; ++i) {
+      const rt_light& l = desc->lights[i];
+      float* o = host + 12 * M + 8 * i;
+      o[0] = l.position[0], o[1] = l.position[1], o[2] = l.position[2], o[3] = 0.f;
+      o[4] = l.intensity[0], o[5] = l.intensity[1], o[6] = l.intensity[2], o[7] = 0.f;
+    }
+    e = hipMemcpyAsync(storage + plan.mats_off, host, mb, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && lb)
+      e = hipMemcpyAsync(storage + plan.lights_off, reinterpret_cast<char*>(host) + mb, lb, hipMemcpyHostToDevice,
+                         stream);
+    // pageable source: wait before freeing it
+    hipError_t e2 = hipStreamSynchronize(stream);
+    std::free(host);
+    SRT_CHECK(e);
+    SRT_CHECK(e2);
+  }
+
+  result->depth = 0;
+  result->max_leaf = T > 0 ? 1 : 0;
+  result->num_nodes = 0;
+  result->root = 0;
+  for (int a = 0; a < 3; ++a) result->lo[a] = result->hi[a] = 0.f;
+
+  float4* recs = reinterpret_cast<float4*>(storage + plan.tris_off);
+  Bounds6 bounds{};
+  int32_t depth = 0;
+  if (T > 0) {
+    float4* lo = reinterpret_cast<float4*>(scratch + plan.lo_off);
+    float4* hi = reinterpret_cast<float4*>(scratch + plan.hi_off);
+    Bounds6* partial = reinterpret_cast<Bounds6*>(scratch + plan.partial_off);
+    k_tri_prep<<<blocks_for(T), kBlock, 0, stream>>>(desc->triangles, desc->tri_material, T, M, lo, hi, partial,
+                                                     status);
+    SRT_LAUNCH_CHECK();
+    k_reduce_bounds<<<1, kBlock, 0, stream>>>(partial, plan.num_blocks_prep);
+    SRT_LAUNCH_CHECK();
+
+    if (plan.bvh) {
+      uint64_t* k0 = reinterpret_cast<uint64_t*>(scratch + plan.keys0_off);
+      uint64_t* k1 = reinterpret_cast<uint64_t*>(scratch + plan.keys1_off);
+      uint32_t* i0 = reinterpret_cast<uint32_t*>(scratch + plan.ids0_off);
+      uint32_t* i1 = reinterpret_cast<uint32_t*>(scratch + plan.ids1_off);
+      uint32_t* hist = reinterpret_cast<uint32_t*>(scratch + plan.hist_off);
+      k_morton<<<blocks_for(T), kBlock, 0, stream>>>(lo, hi, partial, T, k0, i0);
+      SRT_LAUNCH_CHECK();
+      const int64_t nb = plan.num_sort_blocks;
+      for (int pass = 0; pass < 8; ++pass) {
+        int shift = pass * kRadixBits;
+        k_digit_hist<<<unsigned(nb), kBlock, 0, stream>>>(k0, T, shift, hist, nb);
+        SRT_LAUNCH_CHECK();
+        k_scan_exclusive<<<1, 1024, 0, stream>>>(hist, nb * kRadix);
+        SRT_LAUNCH_CHECK();
+        k_scatter<<<unsigned(nb), kBlock, 0, stream>>>(k0, i0, T, shift, hist, nb, k1, i1);
+        SRT_LAUNCH_CHECK();
+        std::swap(k0, k1);
+        std::swap(i0, i1);
+      }
+      // after 8 passes the sorted data is back in the *0 buffers
+      int2* children = reinterpret_cast<int2*>(scratch + plan.children_off);
+      int2* range = reinterpret_cast<int2*>(scratch + plan.range_off);
+      int32_t* parent = reinterpret_cast<int32_t*>(scratch + plan.parent_off);
+      uint32_t* flags = reinterpret_cast<uint32_t*>(scratch + plan.flags_off);
+      float4* nodebox = reinterpret_cast<float4*>(scratch + plan.nodebox_off);
+      int32_t* dmax = reinterpret_cast<int32_t*>(status + 4);
+      k_karras<<<blocks_for(T - 1), kBlock, 0, stream>>>(k0, T, children, parent, range);
+      SRT_LAUNCH_CHECK();
+      k_fill<uint32_t><<<blocks_for(T - 1), kBlock, 0, stream>>>(flags, 0u, T - 1);
+      SRT_LAUNCH_CHECK();
+      k_refit<<<blocks_for(T), kBlock, 0, stream>>>(children, parent, lo, hi, i0, nodebox, flags, T, dmax, status);
+      SRT_LAUNCH_CHECK();
+      // read back the scene bounds for the padding
+      SRT_CHECK(hipMemcpyAsync(&bounds, partial, sizeof(bounds), hipMemcpyDeviceToHost, stream));
+      SRT_CHECK(hipMemcpyAsync(&depth, dmax, sizeof(depth), hipMemcpyDeviceToHost, stream));
+      SRT_CHECK(hipStreamSynchronize(stream));
+      float m = 0.f;
+      for (int a = 0; a < 3; ++a) m = std::max(m, std::max(std::fabs(bounds.blo[a]), std::fabs(bounds.bhi[a])));
+      PackArgs pa;
+      pa.children = children;
+      pa.range = range;
+      pa.leaf_lo = lo;
+      pa.leaf_hi = hi;
+      pa.sorted_ids = i0;
+      pa.nodebox = nodebox;
+      pa.nodes = reinterpret_cast<float4*>(storage + plan.nodes_off);
+      pa.n = T;
+      pa.pad = m * 0x1p-18f + 1e-20f;  // conservative box growth (slab and triangle-test rounding)
+      pa.leaf_size = 1;
+      k_pack_nodes<<<blocks_for(T - 1), kBlock, 0, stream>>>(pa);
+      SRT_LAUNCH_CHECK();
+      k_pack_tris<<<blocks_for(T), kBlock, 0, stream>>>(desc->triangles, desc->tri_material, i0, T, recs);
+      SRT_LAUNCH_CHECK();
+      result->num_nodes = T - 1;
+      result->root = 0;
+    } else {
+      k_pack_tris<<<blocks_for(T), kBlock, 0, stream>>>(desc->triangles, desc->tri_material, nullptr, T, recs);
+      SRT_LAUNCH_CHECK();
+      SRT_CHECK(hipMemcpyAsync(&bounds, partial, sizeof(bounds), hipMemcpyDeviceToHost, stream));
+      result->root = ~0;  // a single leaf holding record 0 (used only when T == 1)
+    }
+  }
+  uint32_t st = 0;
+  SRT_CHECK(hipMemcpyAsync(&st, status, sizeof(st), hipMemcpyDeviceToHost, stream));
+  SRT_CHECK(hipStreamSynchronize(stream));
+  result->status_bits = st;
+  result->depth = depth;
+  for (int a = 0; a < 3; ++a) {
+    result->lo[a] = T > 0 ? bounds.blo[a] : 0.f;
+    result->hi[a] = T > 0 ? bounds.bhi[a] : 0.f;
+  }
+  return hipSuccess;
+#undef SRT_CHECK
+#undef SRT_LAUNCH_CHECK
+}
+
+}  // namespace srt

@@ -1,0 +1,140 @@
+// Internal declarations shared by the library's translation units (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/stereort.h"
+
+namespace srt {
+
+// ---------------------------------------------------------------------------------------------
+// Device scene view (passed by value as a kernel argument)
+// ---------------------------------------------------------------------------------------------
+//
+// BVH2 node, 64 bytes = 4 x float4:
+//   n[0] = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
+//   n[1] = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
+//   n[2] = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
+//   n[3] = (child0, child1, -, -) as int bits
+// A child reference >= 0 is an internal node index; < 0 is a leaf ~(first << 2 | (count - 1)),
+// covering triangle records [first, first + count).
+//
+// Triangle record, 48 bytes = 3 x float4, in leaf order:
+//   r[0] = (v0.xyz, original triangle id as int bits)
+//   r[1] = (e1.xyz = v1 - v0, material as int bits)
+//   r[2] = (e2.xyz = v2 - v0, 0)
+//
+// Primitive keys inside the kernels: triangle record index [0,T), sphere T+s, plane T+S+p.
+// Output ids are the input order (a record carries its original id).
+
+constexpr int kLeafMaxTris = 4;
+constexpr int kNodeFloat4 = 4;
+constexpr int kTriFloat4 = 3;
+constexpr int kMatFloat4 = 3;    // (kd, n), (ks, 0), (kr, 0)
+constexpr int kLightFloat4 = 2;  // (pos, 0), (I, 0)
+constexpr float kSecondaryTmin = 1e-4f;
+constexpr int kStackMax = 128;   // bound on traversal stack depth (BVH depth <= 97 for 63-bit keys)
+
+struct DevScene {
+  const float4* nodes;
+  const float4* tris;
+  const float4* spheres;
+  const uint32_t* sphere_mat;
+  const float4* planes;
+  const uint32_t* plane_mat;
+  const float4* materials;
+  const float4* lights;
+  int32_t T, S, P, L, M;
+  int32_t root;     // node reference of the root; meaningless when T == 0
+  int32_t num_nodes;
+  int32_t has_bvh;  // 0: triangle records are in input order and are brute-forced
+  float ambient[3], background[3];
+};
+
+// Camera constants in FP64 (primary rays are generated in FP64 and rounded once to FP32).
+struct DevCamera {
+  double C[3], f[3], r[3], u[3];
+  double fpx, cx, cy, half_baseline, inv_convergence;
+  int32_t W, H, D;
+  int32_t tiles_x, tiles_y;
+};
+
+// Work counters inside the render workspace (uint32 slots unless noted).
+struct Counters {
+  uint32_t refl_count[RT_MAX_DEPTH + 2];    // entries of the mirror-ray queue at depth d
+  uint32_t shadow_count[RT_MAX_DEPTH + 2];  // shadow records emitted at depth d
+  uint32_t closest_work[RT_MAX_DEPTH + 2];  // persistent work cursor of the closest-hit launch at depth d
+  uint32_t any_work[RT_MAX_DEPTH + 2];      // persistent work cursor of the shadow launch at depth d
+  unsigned long long work[4];               // node visits / tri tests (closest, any)
+  uint32_t pad[16];
+};
+
+// Tile order of paths: a tile of 8x8 pixels of the left eye, then the same tile of the right eye.
+constexpr int kTile = 8;
+constexpr int kPathsPerTile = 2 * kTile * kTile;
+
+struct Scene;  // host handle body
+
+// ---------------------------------------------------------------------------------------------
+// Host-side entry points of the translation units
+// ---------------------------------------------------------------------------------------------
+
+struct BuildPlan {
+  int64_t T;
+  size_t nodes_off, tris_off, spheres_off, sphere_mat_off, planes_off, plane_mat_off, mats_off, lights_off;
+  size_t storage_bytes;
+  // scratch
+  size_t keys0_off, keys1_off, ids0_off, ids1_off, lo_off, hi_off, partial_off, hist_off, children_off,
+      parent_off, flags_off, nodebox_off, status_off, range_off;
+  size_t scratch_bytes;
+  int64_t num_blocks_prep, num_sort_blocks;
+  bool bvh;
+};
+
+BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool bvh);
+
+struct BuildResult {
+  uint32_t status_bits;  // 1 non-finite vertex, 2 triangle material out of range, 4 sphere, 8 plane
+  int32_t depth;
+  int32_t max_leaf;
+  int64_t num_nodes;
+  float lo[3], hi[3];
+  int32_t root;
+};
+
+// Enqueues the LBVH build; blocks until done and reads back BuildResult.
+hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, char* storage, char* scratch,
+                              hipStream_t stream, BuildResult* result);
+
+struct RenderPlan {
+  int64_t chunk_paths;  // paths per pass (multiple of kPathsPerTile)
+  size_t counters_off, ro_off[2], rd_off[2], thr_off[2], hit_off, resinfo_off, so_off, sd_off, contrib_off,
+      vis_off, gstack_off;
+  size_t bytes;
+  int grid_trace;  // persistent workgroups for the traversal kernels
+};
+
+int trace_grid_size(int device);
+size_t plan_render(int64_t chunk_paths, int32_t num_lights, int grid_trace, RenderPlan* plan);
+
+struct TimerImpl;
+void timer_begin(TimerImpl* t, int stage, hipStream_t s);
+void timer_end(TimerImpl* t, int stage, hipStream_t s);
+
+struct RenderArgs {
+  DevScene scene;
+  DevCamera cam;
+  const rt_stereo_output* out;
+  uint32_t flags;
+  char* ws;
+  RenderPlan plan;
+  int64_t path_begin, path_count;
+};
+
+hipError_t render_chunk(const RenderArgs& a, hipStream_t stream, TimerImpl* timer);
+hipError_t add_ray_counts(const RenderArgs& a, hipStream_t stream);
+
+}  // namespace srt

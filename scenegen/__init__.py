@@ -169,18 +169,26 @@ def cube():
 
 
 def dodecahedron():
-    """20 vertices; 12 pentagons found as the 5 vertices farthest along each icosahedron vertex; fan-split."""
+    """20 vertices; its 12 pentagonal faces are the vertex sets that reach the maximum along a face
+    normal (the vertex directions of the dual icosahedron, in the orientation for which exactly five
+    vertices are extreme); each pentagon is fan-split into three triangles."""
     v = [(x, y, z) for x in (-1.0, 1.0) for y in (-1.0, 1.0) for z in (-1.0, 1.0)]
     for s1 in (-1.0, 1.0):
         for s2 in (-1.0, 1.0):
             v += [(0.0, s1 / PHI, s2 * PHI), (s1 / PHI, s2 * PHI, 0.0), (s2 * PHI, 0.0, s1 / PHI)]
     v = np.asarray(v, np.float64)
-    ico, _ = icosahedron()
+    candidates = []
+    for s1 in (-1.0, 1.0):
+        for s2 in (-1.0, 1.0):
+            candidates += [(0.0, s1 * PHI, s2), (s1 * PHI, s2, 0.0), (s2, 0.0, s1 * PHI),
+                           (0.0, s1, s2 * PHI), (s1, s2 * PHI, 0.0), (s2 * PHI, 0.0, s1)]
     faces = []
-    for n in ico:
+    for n in np.asarray(candidates):
+        n = n / np.linalg.norm(n)
         dots = v @ n
-        idx = list(np.argsort(-dots, kind="stable")[:5])
-        faces += _fan(v, idx, n / np.linalg.norm(n))
+        top = np.nonzero(dots > dots.max() - 1e-9)[0]
+        if len(top) == 5:
+            faces += _fan(v, list(top), n)
     assert len(faces) == 36
     return v, _orient_outward(v, faces)
 

@@ -1,0 +1,91 @@
+"""The C ABI on the host: the library loads without a GPU, exports every declared
+function, and validates arguments before touching a device."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from paper_1702_01530_amd import rt
+
+
+def test_library_exports_every_declared_function():
+    L = rt.lib()
+    names = rt.header_functions()
+    assert len(names) >= 14
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing
+    assert set(names) == set(rt._SIGNATURES)
+    assert rt.lib().rt_version() >= 100
+
+
+def _desc(T=10, S=0, P=0, M=1, L=1):
+    d = rt.rt_scene_desc()
+    d.num_triangles, d.num_spheres, d.num_planes, d.num_materials, d.num_lights = T, S, P, M, L
+    return d
+
+
+def test_storage_size_queries():
+    s0, k0 = rt.rt_scene_storage_size(_desc(T=1000))
+    s1, k1 = rt.rt_scene_storage_size(_desc(T=2000))
+    assert s1 > s0 >= 999 * 64 + 1000 * 48 and k1 > k0 > 0
+    d = _desc(T=1000)
+    d.flags = rt.RT_ACCEL_NONE
+    s2, _ = rt.rt_scene_storage_size(d)
+    assert s2 < s0  # no nodes without a BVH
+    s3, _ = rt.rt_scene_storage_size(_desc(T=0, S=3, P=1))
+    assert s3 > 0
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("num_triangles", -1, "num_triangles"),
+    ("num_materials", 0, "num_materials"),
+    ("num_lights", 9, "num_lights"),
+    ("flags", 8, "flags"),
+])
+def test_descriptor_validation(field, value, needle):
+    d = _desc()
+    setattr(d, field, value)
+    with pytest.raises(rt.RtError) as ei:
+        rt.rt_scene_storage_size(d)
+    assert ei.value.status == rt.RT_ERR_INVALID_ARGUMENT
+    assert needle in rt.last_error()
+
+
+def test_build_rejects_bad_pointers_before_device_use():
+    d = _desc(T=5)
+    with pytest.raises(rt.RtError) as ei:
+        rt.rt_scene_build(d, None, 0, None, 0, None)
+    assert ei.value.status == rt.RT_ERR_INVALID_ARGUMENT and "NULL" in str(ei.value)
+    assert rt.lib().rt_scene_build(None, None, 0, None, 0, None, None) == rt.RT_ERR_INVALID_ARGUMENT
+
+
+def test_camera_validation_and_workspace():
+    _, cam = sg.make_terrain_1080p()
+    c = rt.make_camera_struct(cam)
+    full = rt.rt_render_workspace_size(c, 4)
+    mn = rt.rt_render_workspace_min(4)
+    assert full > mn > 0
+    c2 = rt.make_camera_struct(cam.resized(3840, 2160))
+    assert rt.rt_render_workspace_size(c2, 4) > full
+    for field, value in (("hfov_deg", 180.0), ("width", 0), ("max_depth", 9), ("baseline", -1.0)):
+        bad = rt.make_camera_struct(cam)
+        setattr(bad, field, value)
+        with pytest.raises(rt.RtError) as ei:
+            rt.rt_render_workspace_size(bad, 4)
+        assert ei.value.status == rt.RT_ERR_INVALID_ARGUMENT
+    bad = rt.make_camera_struct(cam.with_(forward=np.float32([0, 1, 0])))
+    with pytest.raises(rt.RtError, match="parallel"):
+        rt.rt_render_workspace_size(bad, 4)
+
+
+def test_render_argument_checks_without_device():
+    _, cam = sg.make_spheres_scene()
+    c = rt.make_camera_struct(cam)
+    out = rt.rt_stereo_output()
+    assert rt.lib().rt_render_stereo(None, C.byref(c), C.byref(out), None, 0, 0, None, None, None) == \
+        rt.RT_ERR_INVALID_ARGUMENT
+    assert "scene" in rt.last_error()
+    assert rt.lib().rt_timer_read(None, None) == rt.RT_ERR_INVALID_ARGUMENT
+    t = rt.rt_timer_create()
+    rt.rt_timer_destroy(t)

@@ -1,0 +1,230 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+from tests.helpers import make_scene, material, mono_camera, f32
+from tests.parity import compare, assert_parity, gpu_flat
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_01530_amd import rt
+    rt.lib()
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def render(torch, scene, cam, accel="lbvh", **kw):
+    from paper_1702_01530_amd.stereo import GpuScene, render_stereo
+    gs = GpuScene(scene, accel=accel)
+    out = render_stereo(gs, cam, path_ids=True, **kw)
+    torch.cuda.synchronize()
+    return gs, out
+
+
+def check_parity(torch, scene, cam, samples=None, accel="lbvh", **kw):
+    say(f"[parity] {scene.name} {cam.width}x{cam.height} D={cam.max_depth} accel={accel} "
+        f"samples={'all' if samples is None else len(samples)}")
+    gs, out = render(torch, scene, cam, accel=accel)
+    assert int(out["ray_counts"][7]) == 0, "internal consistency check fired"
+    g = gpu_flat(out)
+    orc = oracle.render(scene, cam, samples=samples)
+    res = compare(g, orc, **kw)
+    say(f"[parity] ties={res['ties']} max_err={res['max_err']:.3g} t_err={res.get('max_rel_t_err', 0):.3g}")
+    assert_parity(res)
+    gs.close()
+    return g, orc, res
+
+
+def test_spheres_full_frame(torch_cuda):
+    scene, cam = sg.make_spheres_scene()
+    g, orc, res = check_parity(torch_cuda, scene, cam, allow_min_one=False)
+    assert res["n"] == 2 * 256 * 256
+
+
+def test_paper5_full_frame_lbvh_and_brute(torch_cuda):
+    scene, cam = sg.make_paper5_scene()
+    gl, _, _ = check_parity(torch_cuda, scene, cam)
+    gb, _, _ = check_parity(torch_cuda, scene, cam, accel="none")
+    for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state"):
+        assert np.array_equal(gl[k], gb[k]), k
+
+
+@pytest.mark.parametrize("grid,spheres,level,lights,depth,size", [
+    (24, 4, 1, 2, 3, (96, 64)),
+    (40, 6, 2, 4, 4, (77, 45)),   # ragged tiles on both axes
+])
+def test_small_terrain_full_frame(torch_cuda, grid, spheres, level, lights, depth, size):
+    scene, cam = sg.make_small_terrain(seed=11 + grid, grid=grid, n_spheres=spheres, level=level, lights=lights,
+                                       depth=depth)
+    cam = cam.resized(*size)
+    g, orc, res = check_parity(torch_cuda, scene, cam)
+    # the LBVH path and the brute-force path agree bitwise
+    gs, ob = render(torch_cuda, scene, cam, brute_force=True)
+    b = gpu_flat(ob)
+    for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state"):
+        assert np.array_equal(g[k], b[k]), k
+    # ray counts: every ray the oracle traced, the GPU traced (ties aside)
+    counts = ob["ray_counts"].cpu().numpy()
+    assert counts[0] == 2 * cam.width * cam.height
+    assert abs(counts[1] - orc["ray_counts"][1]) <= res["ties"] * cam.max_depth
+    assert abs(counts[2] - orc["ray_counts"][2]) <= res["ties"] * (cam.max_depth + 1) * scene.num_lights
+
+
+def test_chunking_and_repeat_bitwise(torch_cuda):
+    torch = torch_cuda
+    from paper_1702_01530_amd import rt
+    from paper_1702_01530_amd.stereo import GpuScene, Workspace, render_stereo
+    scene, cam = sg.make_small_terrain(seed=5, grid=32, n_spheres=5, level=2, lights=3, depth=3)
+    cam = cam.resized(200, 120)  # 2*25*15 tiles = 96000 paths: several minimum-size passes
+    gs = GpuScene(scene)
+    full = render_stereo(gs, cam, path_ids=True)
+    ws_min = Workspace(rt.rt_render_workspace_min(scene.num_lights))
+    small = render_stereo(gs, cam, path_ids=True, workspace=ws_min)
+    again = render_stereo(gs, cam, path_ids=True)
+    torch.cuda.synchronize()
+    for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state"):
+        assert torch.equal(full[k], small[k]), k
+        assert torch.equal(full[k], again[k]), k
+    with pytest.raises(rt.RtError) as ei:
+        render_stereo(gs, cam, workspace=Workspace(ws_min.nbytes - 4096))
+    assert ei.value.status == rt.RT_ERR_BUFFER_TOO_SMALL
+    gs.close()
+
+
+def test_degenerate_scenes(torch_cuda):
+    torch = torch_cuda
+    bg = (0.25, 0.5, 0.75)
+    cam = mono_camera(width=13, height=7, depth=2)
+    # empty scene: every pixel is the background
+    empty = make_scene(background=bg)
+    gs, out = render(torch, empty, cam)
+    assert torch.allclose(out["radiance"].cpu(), torch.tensor(bg, dtype=torch.float32).expand(2, 7, 13, 3))
+    assert (out["hit_prim"].cpu() == -1).all()
+    # a single triangle (a BVH that is one leaf), two triangles, no lights, 1x1 image, depth 0
+    tri = [[-1, 0, 4], [1, 0, 4], [0, 2, 4]]
+    for scene in (make_scene(tris=[tri], background=bg, ambient=(0.1, 0.2, 0.3)),
+                  make_scene(tris=[tri, [[-3, 0, 6], [3, 0, 6], [0, 3, 6]]], lights=[[0, 5, 0, 1, 1, 1]],
+                             materials=[material(kr=(0.5, 0.5, 0.5))], ambient=(0.05,) * 3)):
+        for c in (cam, cam.resized(1, 1), cam.with_(max_depth=0)):
+            check_parity(torch, scene, c, allow_min_one=False)
+
+
+def test_headlight_lambert_closed_form_gpu(torch_cuda):
+    """Sphere lit from the eye: radiance = rho I cos(theta) + ks I max(0, cos 2theta)^n (closed form)."""
+    c = np.array([0.3, 0.9, 6.0])
+    r = 1.3
+    rho = np.array([0.7, 0.4, 0.2])
+    I = np.array([0.9, 1.1, 0.5])
+    eye = np.array([0.0, 1.0, 0.0])
+    scene = make_scene(spheres=[list(c) + [r]], materials=[material(kd=rho, ks=(0.5, 0.5, 0.5))],
+                       lights=[list(eye) + list(I)], background=(0.1, 0.2, 0.3))
+    cam = mono_camera(center=eye, width=48, height=48, hfov=30.0)
+    gs, out = render(torch_cuda, scene, cam)
+    L = out["radiance"][0].cpu().numpy().astype(np.float64)
+    cf, rf, rhof, If = f32(c), f32(r), f32(rho), f32(I)
+    n = 0
+    for j in range(48):
+        for i in range(48):
+            O, d = oracle.primary_ray(cam, 0, i, j)
+            w = cf - O
+            h = np.linalg.norm(w - (w @ d) * d)
+            if abs(h - rf) < 1e-3:
+                continue
+            if h < rf:
+                q = (h / rf) ** 2
+                expect = rhof * If * math.sqrt(1 - q) + 0.5 * If * max(0.0, 1 - 2 * q) ** 32
+                n += 1
+            else:
+                expect = f32([0.1, 0.2, 0.3])
+            np.testing.assert_allclose(L[j, i], expect, atol=1e-4)
+    assert n > 400
+    assert np.array_equal(out["radiance"][0].cpu().numpy(), out["radiance"][1].cpu().numpy())
+
+
+def test_pinned_readback_and_timer(torch_cuda):
+    torch = torch_cuda
+    from paper_1702_01530_amd.stereo import GpuScene, render_stereo, Timer
+    scene, cam = sg.make_spheres_scene()
+    gs = GpuScene(scene, accel="none")
+    timer = Timer()
+    copy = torch.cuda.Stream()
+    out = render_stereo(gs, cam, host=True, copy_stream=copy, timer=timer.handle)
+    copy.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(out["host_radiance"], out["radiance"].cpu())
+    t = timer.read()
+    assert t["trace_closest"][1] == cam.max_depth + 1 and t["trace_closest"][0] > 0
+    assert t["readback"][1] == 1 and t["readback"][0] > 0
+    timer.close()
+    gs.close()
+
+
+def test_invalid_arguments_gpu(torch_cuda):
+    torch = torch_cuda
+    from paper_1702_01530_amd import rt
+    from paper_1702_01530_amd.stereo import GpuScene
+    scene, _ = sg.make_paper5_scene()
+    bad = make_scene(tris=scene.triangles.copy())
+    bad.triangles[3, 1, 2] = np.nan
+    with pytest.raises(rt.RtError) as ei:
+        GpuScene(bad)
+    assert ei.value.status == rt.RT_ERR_INVALID_ARGUMENT and "finite" in str(ei.value)
+    bad = make_scene(tris=scene.triangles, tri_mat=np.full(scene.num_triangles, 7))
+    with pytest.raises(rt.RtError) as ei:
+        GpuScene(bad)
+    assert "material" in str(ei.value)
+    bad = make_scene(spheres=[[0, 0, 5, -1.0]])
+    with pytest.raises(rt.RtError):
+        GpuScene(bad)
+
+
+def test_bvh_structure(torch_cuda):
+    from paper_1702_01530_amd.stereo import GpuScene
+    scene, _ = sg.make_small_terrain(seed=3, grid=48, n_spheres=8, level=2)
+    gs = GpuScene(scene)
+    info = gs.info()
+    T = scene.num_triangles
+    assert info["num_nodes"] == T - 1 and info["node_bytes"] == 64 * (T - 1)
+    assert math.log2(T) <= info["bvh_depth"] <= 96
+    lo, hi = scene.triangles.reshape(-1, 3).min(0), scene.triangles.reshape(-1, 3).max(0)
+    assert np.array_equal(np.array(info["bounds_lo"], np.float32), lo)
+    assert np.array_equal(np.array(info["bounds_hi"], np.float32), hi)
+    gs.close()
+
+
+@pytest.fixture(scope="module")
+def terrain_212k():
+    return sg.make_terrain_1080p()
+
+
+@pytest.fixture(scope="module")
+def terrain_3m():
+    return sg.make_terrain_3m()
+
+
+def test_terrain212k_1080p_sampled(torch_cuda, terrain_212k):
+    scene, cam = terrain_212k
+    samples = sg.sample_paths(cam, 1024, seed=21)
+    check_parity(torch_cuda, scene, cam, samples=samples)
+
+
+def test_terrain3m_1080p_sampled(torch_cuda, terrain_3m):
+    """The benchmark workload at its full size, in the launch configuration the benchmark times."""
+    scene, cam = terrain_3m
+    samples = sg.sample_paths(cam, 384, seed=31)
+    check_parity(torch_cuda, scene, cam, samples=samples)
