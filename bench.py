@@ -1,0 +1,234 @@
+"""Benchmark: stereo Whitted ray tracing throughput on one MI355X.
+
+One step = one stereo frame (both eyes, every ray of the Whitted tree: primary,
+shadow and mirror rays) of the 3.4M-triangle terrain scene at 1920x1080 per eye,
+reflection depth 4, 4 point lights.  Inputs are seeded and synthetic and are
+resident in HBM (the scene is built once) before the timed region starts.
+
+Prints one JSON line.  `value` is Mrays/s (all rays of the frame / device time
+per frame); stereo frames/s is reported beside it, device-only and end to end
+(including the pinned asynchronous readback of both eyes' radiance).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s and stereo frames/s (1080p, 2M tris) at 1 GPU; p50/p99 latency served"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes (what the traversal must read and write if nothing were cached).
+NODE_BYTES = 64      # one BVH2 node visit
+TRI_BYTES = 48       # one triangle record test
+CLOSEST_RAY_IO = 32 + 8   # ray in (origin+path, direction+exclude) + hit out (t, key)
+ANY_RAY_IO = 32 + 1       # shadow record in + visibility byte out
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    import scenegen as sg
+    if name == "terrain3.4M_1080p":
+        return sg.make_terrain_3m()
+    if name == "terrain3.4M_4k":
+        s, c = sg.make_terrain_3m()
+        return s, c.resized(3840, 2160)
+    if name == "terrain212k_1080p":
+        return sg.make_terrain_1080p()
+    if name == "spheres8_256":
+        return sg.make_spheres_scene()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(scene, cam, target_s: float = 15.0) -> dict:
+    """The FP64 brute-force oracle on a seeded sample of the same frame's paths, timed on the host."""
+    import numpy as np
+    import oracle
+    import scenegen as sg
+    threads = oracle.default_threads()
+    n = threads * 2
+    while True:
+        t0 = time.perf_counter()
+        r = oracle.render(scene, cam, samples=sg.sample_paths(cam, n, seed=99), nthreads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= target_s * 0.66 or n >= 2 * cam.width * cam.height:
+            break
+        n = int(min(2 * cam.width * cam.height, max(2 * n, n * target_s / max(dt, 1e-3))))
+    rays = int(r["ray_counts"].sum())
+    return {"value": rays / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} seeded paths of the same stereo frame ({rays} rays, FP64 brute force over all "
+                      f"{scene.num_prims} primitives per ray, {dt:.1f} s)",
+            "seconds": dt, "paths": n}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="terrain3.4M_1080p")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-end-to-end", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for scaling HBM traffic counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the render path has no multi-GPU "
+                                   "mode (each GPU would render its own tiles with no exchange)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1702_01530_amd import rt
+    from paper_1702_01530_amd.stereo import GpuScene, Workspace, alloc_outputs, render_stereo, Timer
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        n = 1 << 30
+        a = torch.empty(n, dtype=torch.uint8, device=dev)
+        b = torch.empty(n, dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 3}))
+        return
+
+    rt.lib()
+    scene, cam = workload(args.workload)
+    log(f"[bench] workload {args.workload}: {scene.num_triangles} triangles, {cam.width}x{cam.height} per eye, "
+        f"depth {cam.max_depth}, {scene.num_lights} lights")
+    t0 = time.perf_counter()
+    gs = GpuScene(scene)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    info = gs.info()
+    log(f"[bench] scene built in {build_ms:.1f} ms (incl. upload), BVH depth {info['bvh_depth']}")
+
+    ws = Workspace.for_camera(cam, gs.num_lights)
+    out = alloc_outputs(cam, gs.num_lights, dev)
+
+    # work counts for the algorithmic-byte figures (instrumented kernels, not timed)
+    out["ray_counts"].zero_()
+    render_stereo(gs, cam, count_work=True, workspace=ws, outputs=out)
+    torch.cuda.synchronize()
+    cnt = out["ray_counts"].cpu().numpy().astype(np.int64)
+    if cnt[7] != 0:
+        raise SystemExit("internal consistency check fired during the counting pass")
+    rays = int(cnt[0] + cnt[1] + cnt[2])
+    closest_rays, any_rays = int(cnt[0] + cnt[1]), int(cnt[2])
+    closest_bytes = NODE_BYTES * cnt[3] + TRI_BYTES * cnt[4] + CLOSEST_RAY_IO * closest_rays
+    any_bytes = NODE_BYTES * cnt[5] + TRI_BYTES * cnt[6] + ANY_RAY_IO * any_rays
+    log(f"[bench] rays/frame {rays} (primary {cnt[0]}, mirror {cnt[1]}, shadow {cnt[2]}); "
+        f"closest: {cnt[3] / max(closest_rays, 1):.1f} nodes + {cnt[4] / max(closest_rays, 1):.1f} tris per ray; "
+        f"shadow: {cnt[5] / max(any_rays, 1):.1f} nodes + {cnt[6] / max(any_rays, 1):.1f} tris per ray")
+
+    for _ in range(args.warmup):
+        render_stereo(gs, cam, workspace=ws, outputs=out)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} frames)")
+
+    timer = Timer()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    frame_ms = []
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        render_stereo(gs, cam, workspace=ws, outputs=out, timer=timer.handle)
+        e1.record()
+        frame_ms.append((e0, e1))
+    stop.record()
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t_wall
+    total_ms = start.elapsed_time(stop)
+    per_frame = [a.elapsed_time(b) for a, b in frame_ms]
+    ms_per_step = total_ms / args.steps
+    stages = timer.read()
+    log(f"[bench] timed {args.steps} frames: {ms_per_step:.3f} ms/frame (median {np.median(per_frame):.3f}), "
+        f"wall {wall_s:.2f} s")
+    for k, (ms, n) in stages.items():
+        if n:
+            log(f"[bench]   {k:14s} {ms / args.steps:8.3f} ms/frame over {n // args.steps} launches/frame")
+
+    # end to end: render + pinned async readback on a side stream, double-buffered
+    e2e = None
+    if not args.no_end_to_end:
+        outs = [alloc_outputs(cam, gs.num_lights, dev, host=True, counts=False) for _ in range(2)]
+        copy = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        done = []
+        for i in range(args.steps):
+            o = outs[i % 2]
+            if i >= 2:
+                done[i - 2].synchronize()  # the host buffer of two frames ago has been consumed
+            render_stereo(gs, cam, workspace=ws, outputs=o, copy_stream=copy)
+            ev = torch.cuda.Event()
+            ev.record(copy)
+            done.append(ev)
+        copy.synchronize()
+        torch.cuda.synchronize()
+        e2e = (time.perf_counter() - t1) * 1e3 / args.steps
+        log(f"[bench] end to end with pinned readback: {e2e:.3f} ms/frame")
+
+    # the dominant kernel is the fused traversal (closest-hit rays of depth d + shadow rays of depth d-1)
+    trace_total_ms, trace_launches = stages["trace"]
+    launches_per_frame = trace_launches / args.steps
+    bytes_per_launch = (closest_bytes + any_bytes) / launches_per_frame
+    avg_launch_ms = trace_total_ms / trace_launches
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+
+    res = {
+        "metric": METRIC,
+        "value": rays / (ms_per_step * 1e-3) / 1e6,
+        "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "triangles": scene.num_triangles, "width": cam.width,
+                   "height": cam.height, "eyes": 2, "max_depth": cam.max_depth, "lights": scene.num_lights,
+                   "accel": "lbvh"},
+        "stereo_fps": 1e3 / ms_per_step,
+        "stereo_fps_end_to_end": (1e3 / e2e) if e2e else None,
+        "ms_per_step_end_to_end": e2e,
+        "ms_per_step_p50": float(np.median(per_frame)),
+        "rays_per_frame": rays,
+        "ray_counts": {"primary": int(cnt[0]), "mirror": int(cnt[1]), "shadow": int(cnt[2])},
+        "stage_ms_per_frame": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
+        "build_ms": build_ms,
+        "roofline": {
+            "bound": "hbm", "kernel": "k_trace",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms,
+            "launches_per_frame": launches_per_frame,
+            "bytes_per_frame": {"closest": int(closest_bytes), "shadow": int(any_bytes)},
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a host sample ...")
+        res["cpu_baseline"] = cpu_baseline(scene, cam)
+        log(f"[bench] cpu baseline {res['cpu_baseline']['value']:.4f} Mrays/s on {res['cpu_baseline']['cores']} threads")
+    timer.close()
+    gs.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

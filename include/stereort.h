@@ -231,12 +231,11 @@ rt_status rt_render_batch(const rt_batch_item* items, int32_t n, void* workspace
  * ------------------------------------------------------------------------------------------- */
 
 enum {
-  RT_STAGE_TRACE_CLOSEST = 0, /* closest-hit traversal (primary and mirror rays) */
-  RT_STAGE_TRACE_ANY = 1,     /* shadow-ray traversal */
-  RT_STAGE_SHADE = 2,         /* shading and ray spawning */
-  RT_STAGE_RESOLVE = 3,       /* shadow resolve / compositing */
-  RT_STAGE_SETUP = 4,         /* queue resets */
-  RT_STAGE_READBACK = 5,      /* device-to-host copy */
+  RT_STAGE_TRACE = 0,    /* BVH traversal: closest-hit rays of depth d fused with shadow rays of depth d-1 */
+  RT_STAGE_SHADE = 1,    /* shading and ray spawning */
+  RT_STAGE_RESOLVE = 2,  /* adding the unoccluded lights' terms */
+  RT_STAGE_SETUP = 3,    /* queue resets and counter updates */
+  RT_STAGE_READBACK = 4, /* device-to-host copy */
   RT_NUM_STAGES = 8
 };
 

@@ -357,7 +357,7 @@ rt_status rt_scene_build(const rt_scene_desc* desc, void* storage, size_t storag
   info.num_lights = desc->num_lights;
   info.num_materials = desc->num_materials;
   info.bvh_depth = plan.bvh ? res.depth : 0;
-  info.leaf_size = desc->num_triangles > 0 ? 1 : 0;
+  info.leaf_size = desc->num_triangles > 0 ? (plan.bvh ? srt::leaf_size() : 1) : 0;
   info.num_nodes = res.num_nodes;
   info.node_bytes = res.num_nodes * 64;
   info.triangle_bytes = desc->num_triangles * 48;

@@ -23,7 +23,14 @@
 
 #include "rt_internal.h"
 
+#ifndef SRT_LEAF_SIZE
+#define SRT_LEAF_SIZE 1
+#endif
+
 namespace srt {
+
+int leaf_size() { return SRT_LEAF_SIZE; }
+
 namespace {
 
 constexpr int kBlock = 256;
@@ -644,7 +651,7 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
       pa.nodes = reinterpret_cast<float4*>(storage + plan.nodes_off);
       pa.n = T;
       pa.pad = m * 0x1p-18f + 1e-20f;  // conservative box growth (slab and triangle-test rounding)
-      pa.leaf_size = 1;
+      pa.leaf_size = SRT_LEAF_SIZE;
       k_pack_nodes<<<blocks_for(T - 1), kBlock, 0, stream>>>(pa);
       SRT_LAUNCH_CHECK();
       k_pack_tris<<<blocks_for(T), kBlock, 0, stream>>>(desc->triangles, desc->tri_material, i0, T, recs);

@@ -1,17 +1,22 @@
 // Stereo Whitted ray tracing on gfx950: wavefront-persistent kernels.
 //
-// Per pass over a range of paths (a path = one pixel of one eye), for each ray
-// depth d = 0..D:
-//   k_closest<d==0>  persistent closest-hit traversal (primary rays generated
-//                    in FP64 in-register for both eyes: the paper's parallel
-//                    levels 1 and 2 share one launch and one queue)
-//   k_shade          Phong shading, shadow-ray and mirror-ray spawning; wave
-//                    ballots + prefix sums compact the new rays into queues
-//   k_any            persistent any-hit traversal of the shadow queue
-//   k_resolve        adds the unoccluded lights' terms in fixed light order
-// Every pixel is owned by one queue entry per depth and its radiance is
-// accumulated in a fixed order, so results are bitwise independent of queue
-// order, pass size and what else shares the GPU.
+// A pass renders a range of paths (a path = one pixel of one eye; an 8x8 tile
+// of the left eye is followed by the same tile of the right eye, so both of
+// the paper's parallel levels -- the two channels and the pixels inside each
+// -- share one queue and one launch).  With D mirror bounces, for d = 0..D+1:
+//   k_trace(d)    persistent BVH traversal of the closest-hit rays of depth d
+//                 (primary rays generated in-register, FP64 rounded once to
+//                 FP32) together with the shadow rays spawned at depth d-1;
+//                 the two ray kinds fill one grid, so neither leaves a tail
+//   k_shade(d)    Phong shading of the depth-d hits: adds the ambient (or
+//                 background) term, spawns one shadow ray per light with
+//                 N.L > 0 into that light's queue and a mirror ray into the
+//                 next depth's queue; queues are compacted with wave ballots
+//                 and one atomic per block and queue
+//   k_resolve(d-1) adds the unoccluded lights' terms of depth d-1 in light order
+// Queues and per-depth buffers are double-buffered by depth parity.  Every
+// pixel's radiance is accumulated by one thread at a time in a fixed order,
+// so results do not depend on queue order, pass size or concurrent work.
 
 #include <hip/hip_runtime.h>
 
@@ -20,14 +25,22 @@
 
 #include "rt_internal.h"
 
+#ifndef SRT_STACK_LDS
+#define SRT_STACK_LDS 16
+#endif
+#ifndef SRT_TRACE_WAVES_PER_EU
+#define SRT_TRACE_WAVES_PER_EU 0
+#endif
+
 namespace srt {
 namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kStackLds = 32;                       // traversal stack entries per lane kept in LDS
-constexpr int kStackGlobal = 96 - kStackLds;        // spill entries per lane in the workspace
+constexpr int kStackLds = SRT_STACK_LDS;       // traversal stack entries per lane kept in LDS (power of two)
+constexpr int kStackGlobal = 96 - kStackLds;   // older entries spill to the workspace
 constexpr int kMaxTraceBlocks = 2048;
+static_assert((kStackLds & (kStackLds - 1)) == 0, "LDS stack size must be a power of two");
 
 // ---------------------------------------------------------------------------------------------
 // Small vector helpers
@@ -52,15 +65,17 @@ __device__ inline float safe_rcp(float x) {
   return 1.0f / x;
 }
 
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+
 __device__ inline uint64_t lanemask_lt() {
-  const int lane = threadIdx.x & 63;
+  const int lane = lane_id();
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-__device__ inline int lane_id() { return threadIdx.x & 63; }
-
 // Next float above a non-negative x (+inf stays +inf): lets a `t < tmax` test admit t == x.
 __device__ inline float next_up(float x) { return x == INFINITY ? x : __int_as_float(__float_as_int(x) + 1); }
+
+__device__ inline uint32_t round64(uint32_t x) { return (x + 63u) & ~63u; }
 
 // ---------------------------------------------------------------------------------------------
 // Kernel arguments
@@ -70,15 +85,15 @@ struct KArgs {
   DevScene sc;
   DevCamera cam;
   Counters* ctr;
-  float4* ro[2];   // ray queues (ping-pong by depth parity): origin + path id bits
-  float4* rd[2];   // direction + excluded primitive key bits
-  float4* thr[2];  // throughput
-  float2* hit;     // (t, key bits)
-  uint2* resinfo;  // (first shadow record, light mask)
-  float4* so;      // shadow origin + tmax
-  float4* sd;      // shadow direction + excluded key bits
-  float4* contrib; // light term x throughput
-  uint8_t* vis;    // 1 = light visible
+  float4* ro[2];       // mirror/primary ray queue by depth parity: origin + path id bits
+  float4* rd[2];       // direction + excluded primitive key bits
+  float4* thr[2];      // throughput
+  float2* hit;         // (t, key bits) of the closest-hit rays of the current depth
+  uint2* resinfo[2];   // per entry of a depth: (path id, mask of lights with a shadow ray)
+  float4* srec[2];     // shadow records [L][cap]: (origin, excluded key bits)
+  uint32_t* sowner[2]; // [L][cap]: entry that owns the record
+  float4* contrib[2];  // [cap][L]: the light's term times throughput
+  uint8_t* vis[2];     // [cap][L]: 1 = light visible
   uint32_t* gstack;
   float* radiance[2];
   float* hit_t[2];
@@ -86,6 +101,7 @@ struct KArgs {
   int32_t* path_prims[2];
   uint8_t* shadow_state[2];
   int64_t path_begin, path_count;
+  uint32_t cap;           // entries per queue
   int32_t brute;
   int32_t trace_threads;  // threads in the persistent traversal grid (gstack stride)
 };
@@ -166,7 +182,7 @@ __device__ inline float plane_t(float4 p, float3 o, float3 d, float tmin, float 
   return (t > tmin && t < tmax) ? t : INFINITY;
 }
 
-// Slab test of one child box; returns entry distance, or +inf when missed.
+// Slab test of one child box; returns the entry distance, or +inf when missed.
 __device__ inline float slab(float lox, float hix, float loy, float hiy, float loz, float hiz, float3 inv, float3 oi,
                              float tmin, float tmax) {
   const float x0 = fmaf(lox, inv.x, -oi.x), x1 = fmaf(hix, inv.x, -oi.x);
@@ -178,13 +194,13 @@ __device__ inline float slab(float lox, float hix, float loy, float hiy, float l
 }
 
 // ---------------------------------------------------------------------------------------------
-// Traversal stack: kStackLds entries per lane in LDS (ring), older entries spilled to
+// Traversal stack: kStackLds entries per lane in LDS used as a ring; older entries spill to
 // a lane-interleaved area of the workspace.
 // ---------------------------------------------------------------------------------------------
 
 struct Stack {
-  uint32_t* lds;     // &lds_stack[0][threadIdx.x], stride kBlock
-  uint32_t* global;  // &gstack[global thread], stride trace_threads
+  uint32_t* lds;     // &lds_stack[threadIdx.x], stride kBlock
+  uint32_t* global;  // &gstack[global thread], stride gstride
   int gstride;
   int sp;
   bool overflow;
@@ -214,148 +230,63 @@ struct Best {
   int id;
 };
 
-template <bool COUNT>
-__device__ inline void test_leaf_closest(const DevScene& sc, int first, int count, float3 o, float3 d, float tmin,
-                                         int exclude, Best& best, uint32_t& ntris) {
-  for (int k = 0; k < count; ++k) {
-    const int r = first + k;
-    int id;
-    const float t = tri_t(sc.tris, r, o, d, tmin, best.t, &id);
-    if (COUNT) ++ntris;
-    if (r != exclude && (t < best.t || (t == best.t && t < INFINITY && id < best.id))) {
-      best.t = t;
-      best.key = r;
-      best.id = id;
-    }
-  }
-}
-
-// Closest hit: minimum t, exact ties to the smaller original id.
-template <bool COUNT>
-__device__ Best closest_hit(const DevScene& sc, float3 o, float3 d, float tmin, int exclude, bool brute, Stack& st,
-                            uint32_t& nnodes, uint32_t& ntris) {
-  Best best{INFINITY, -1, 0x7fffffff};
-  // Candidates are tested against tmax = next_up(best.t) so that an exact tie in t reaches the
-  // explicit (t, id) comparison; boxes entered exactly at best.t are not culled either.
-  if (sc.T > 0) {
-    if (brute || !sc.has_bvh) {
-      for (int r = 0; r < sc.T; ++r) {
-        int id;
-        const float t = tri_t(sc.tris, r, o, d, tmin, next_up(best.t), &id);
-        if (COUNT) ++ntris;
-        if (r != exclude && (t < best.t || (t == best.t && t < INFINITY && id < best.id))) {
-          best.t = t;
-          best.key = r;
-          best.id = id;
-        }
-      }
-    } else {
-      const float3 inv = make_float3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
-      const float3 oi = mul(o, inv);
-      int node = sc.root;
-      st.sp = 0;
-      // A valid tree visits each node at most once; the cap only guards against a corrupt one.
-      for (int64_t guard = 2 * int64_t(sc.T) + 64; guard > 0; --guard) {
-        if (node >= 0) {
-          if (node >= sc.num_nodes) {  // corrupt reference: stop this ray, never read out of bounds
-            st.overflow = true;
-            break;
-          }
-          const float4* n = sc.nodes + 4 * node;
-          const float4 a = n[0], b = n[1], c = n[2], e = n[3];
-          if (COUNT) ++nnodes;
-          const float tmax = next_up(best.t);
-          const float t0 = slab(a.x, a.y, a.z, a.w, c.x, c.y, inv, oi, tmin, tmax);
-          const float t1 = slab(b.x, b.y, b.z, b.w, c.z, c.w, inv, oi, tmin, tmax);
-          const int c0 = __float_as_int(e.x), c1 = __float_as_int(e.y);
-          const bool h0 = t0 < INFINITY, h1 = t1 < INFINITY;
-          if (h0 && h1) {
-            const bool first0 = t0 <= t1;
-            st.push(first0 ? c1 : c0);
-            node = first0 ? c0 : c1;
-          } else if (h0) {
-            node = c0;
-          } else if (h1) {
-            node = c1;
-          } else {
-            if (st.sp == 0) break;
-            node = st.pop();
-          }
-        } else {
-          const int code = ~node;
-          const int first = code >> 2, count = (code & 3) + 1;
-          if (first + count > sc.T) {
-            st.overflow = true;
-            break;
-          }
-          for (int k = 0; k < count; ++k) {
-            const int r = first + k;
-            int id;
-            const float t = tri_t(sc.tris, r, o, d, tmin, next_up(best.t), &id);
-            if (COUNT) ++ntris;
-            if (r != exclude && (t < best.t || (t == best.t && t < INFINITY && id < best.id))) {
-              best.t = t;
-              best.key = r;
-              best.id = id;
-            }
-          }
-          if (st.sp == 0) break;
-          node = st.pop();
-        }
-      }
-    }
-  }
-  for (int s = 0; s < sc.S; ++s) {
-    const int key = sc.T + s;
-    const float t = sphere_t(sc.spheres[s], o, d, tmin, next_up(best.t));
-    if (key != exclude && (t < best.t || (t == best.t && t < INFINITY && key < best.id))) {
+// ANY = false: closest hit, minimum t, exact ties to the smaller original id; best.t starts at +inf.
+// ANY = true : occlusion, stops at the first primitive with t in (tmin, best.t); best.key >= 0 if found.
+// Candidates are tested against next_up(best.t) in the closest-hit case so that an exact tie in t
+// reaches the (t, id) comparison, and boxes entered exactly at best.t are not culled.
+template <bool ANY, bool COUNT>
+__device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tmin, int exclude, bool brute,
+                                Best& best, Stack& st, uint32_t& nnodes, uint32_t& ntris) {
+  auto accept = [&](float t, int key, int id) -> bool {  // returns true when the traversal can stop
+    if (key == exclude || !(t < INFINITY)) return false;
+    if (ANY) {
       best.t = t;
       best.key = key;
-      best.id = key;
+      best.id = id;
+      return true;
     }
+    if (t < best.t || (t == best.t && id < best.id)) {
+      best.t = t;
+      best.key = key;
+      best.id = id;
+    }
+    return false;
+  };
+  auto limit = [&]() { return ANY ? best.t : next_up(best.t); };
+
+  for (int s = 0; s < sc.S; ++s) {
+    const int key = sc.T + s;
+    if (accept(sphere_t(sc.spheres[s], o, d, tmin, limit()), key, key)) return;
   }
   for (int p = 0; p < sc.P; ++p) {
     const int key = sc.T + sc.S + p;
-    const float t = plane_t(sc.planes[p], o, d, tmin, next_up(best.t));
-    if (key != exclude && (t < best.t || (t == best.t && t < INFINITY && key < best.id))) {
-      best.t = t;
-      best.key = key;
-      best.id = key;
-    }
+    if (accept(plane_t(sc.planes[p], o, d, tmin, limit()), key, key)) return;
   }
-  return best;
-}
-
-// Occlusion: any primitive other than `exclude` with t in (tmin, tmax).
-template <bool COUNT>
-__device__ bool any_hit(const DevScene& sc, float3 o, float3 d, float tmin, float tmax, int exclude, bool brute,
-                        Stack& st, uint32_t& nnodes, uint32_t& ntris) {
-  for (int s = 0; s < sc.S; ++s)
-    if (sc.T + s != exclude && sphere_t(sc.spheres[s], o, d, tmin, tmax) < INFINITY) return true;
-  for (int p = 0; p < sc.P; ++p)
-    if (sc.T + sc.S + p != exclude && plane_t(sc.planes[p], o, d, tmin, tmax) < INFINITY) return true;
-  if (sc.T == 0) return false;
+  if (sc.T == 0) return;
   if (brute || !sc.has_bvh) {
     for (int r = 0; r < sc.T; ++r) {
       int id;
+      const float t = tri_t(sc.tris, r, o, d, tmin, limit(), &id);
       if (COUNT) ++ntris;
-      if (r != exclude && tri_t(sc.tris, r, o, d, tmin, tmax, &id) < INFINITY) return true;
+      if (accept(t, r, id)) return;
     }
-    return false;
+    return;
   }
   const float3 inv = make_float3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
   const float3 oi = mul(o, inv);
   int node = sc.root;
   st.sp = 0;
+  // A valid tree visits each node at most once; the cap only guards against a corrupt one.
   for (int64_t guard = 2 * int64_t(sc.T) + 64; guard > 0; --guard) {
     if (node >= 0) {
-      if (node >= sc.num_nodes) {
+      if (node >= sc.num_nodes) {  // corrupt reference: stop this ray, never read out of bounds
         st.overflow = true;
-        return false;
+        return;
       }
       const float4* n = sc.nodes + 4 * node;
       const float4 a = n[0], b = n[1], c = n[2], e = n[3];
       if (COUNT) ++nnodes;
+      const float tmax = limit();
       const float t0 = slab(a.x, a.y, a.z, a.w, c.x, c.y, inv, oi, tmin, tmax);
       const float t1 = slab(b.x, b.y, b.z, b.w, c.z, c.w, inv, oi, tmin, tmax);
       const int c0 = __float_as_int(e.x), c1 = __float_as_int(e.y);
@@ -364,33 +295,35 @@ __device__ bool any_hit(const DevScene& sc, float3 o, float3 d, float tmin, floa
         const bool first0 = t0 <= t1;
         st.push(first0 ? c1 : c0);
         node = first0 ? c0 : c1;
-      } else if (h0) {
+        continue;
+      }
+      if (h0) {
         node = c0;
-      } else if (h1) {
+        continue;
+      }
+      if (h1) {
         node = c1;
-      } else {
-        if (st.sp == 0) return false;
-        node = st.pop();
+        continue;
       }
     } else {
       const int code = ~node;
       const int first = code >> 2, count = (code & 3) + 1;
       if (first + count > sc.T) {
         st.overflow = true;
-        return false;
+        return;
       }
       for (int k = 0; k < count; ++k) {
         const int r = first + k;
         int id;
+        const float t = tri_t(sc.tris, r, o, d, tmin, limit(), &id);
         if (COUNT) ++ntris;
-        if (r != exclude && tri_t(sc.tris, r, o, d, tmin, tmax, &id) < INFINITY) return true;
+        if (accept(t, r, id)) return;
       }
-      if (st.sp == 0) return false;
-      node = st.pop();
     }
+    if (st.sp == 0) return;
+    node = st.pop();
   }
   st.overflow = true;
-  return false;
 }
 
 __device__ inline void add_work(Counters* ctr, int slot, uint32_t v) {
@@ -400,84 +333,102 @@ __device__ inline void add_work(Counters* ctr, int slot, uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Kernels
+// k_trace: closest-hit rays of depth `depth` and shadow rays of depth `depth - 1` in one
+// persistent grid.  The work space is [closest rays | shadow rays of light 0 | light 1 | ...],
+// each range padded to a multiple of 64 so that every wave batch is one kind of ray.
 // ---------------------------------------------------------------------------------------------
 
-template <bool PRIMARY, bool COUNT>
-__global__ __launch_bounds__(kBlock) void k_closest(KArgs a, int depth) {
-  __shared__ uint32_t lstack[kStackLds * kBlock];
-  const int lane = lane_id();
-  const int gtid = blockIdx.x * kBlock + threadIdx.x;
-  Stack st{&lstack[threadIdx.x], a.gstack + gtid, a.trace_threads, 0, false};
-  const int q = depth & 1;
-  const uint32_t total = PRIMARY ? uint32_t(a.path_count) : a.ctr->refl_count[depth];
-  const float tmin = PRIMARY ? 0.0f : kSecondaryTmin;
-  uint32_t nnodes = 0, ntris = 0;
-  while (true) {
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(&a.ctr->closest_work[depth], 64u);
-    base = __shfl(base, 0);
-    if (base >= total) break;
-    const uint32_t e = base + lane;
-    if (e < total) {
-      float3 o, d;
-      int exclude = -1;
-      bool valid = true;
-      if (PRIMARY) {
-        int eye, x, y;
-        const int64_t p = a.path_begin + e;
-        valid = path_pixel(a.cam, p, &eye, &x, &y);
-        if (valid) {
-          primary_ray(a.cam, eye, x, y, &o, &d);
-          a.ro[q][e] = make_float4(o.x, o.y, o.z, __int_as_float(int(p)));
-          a.rd[q][e] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
-        } else {
-          a.ro[q][e] = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
-        }
-      } else {
-        const float4 ro = a.ro[q][e], rd = a.rd[q][e];
-        o = f3(ro);
-        d = f3(rd);
-        exclude = __float_as_int(rd.w);
-      }
-      if (valid) {
-        Best b = closest_hit<COUNT>(a.sc, o, d, tmin, exclude, a.brute != 0, st, nnodes, ntris);
-        a.hit[e] = make_float2(b.t, __int_as_float(b.key));
-      }
-    }
-  }
-  if (st.overflow) atomicOr(&a.ctr->pad[1], 1u);
-  if (COUNT) {
-    add_work(a.ctr, 0, nnodes);
-    add_work(a.ctr, 1, ntris);
-  }
-}
+#if SRT_TRACE_WAVES_PER_EU > 0
+#define SRT_TRACE_ATTR __attribute__((amdgpu_waves_per_eu(SRT_TRACE_WAVES_PER_EU, SRT_TRACE_WAVES_PER_EU)))
+#else
+#define SRT_TRACE_ATTR
+#endif
 
 template <bool COUNT>
-__global__ __launch_bounds__(kBlock) void k_any(KArgs a, int depth) {
+__global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int depth) {
   __shared__ uint32_t lstack[kStackLds * kBlock];
   const int lane = lane_id();
   const int gtid = blockIdx.x * kBlock + threadIdx.x;
   Stack st{&lstack[threadIdx.x], a.gstack + gtid, a.trace_threads, 0, false};
-  const uint32_t total = a.ctr->shadow_count[depth];
-  uint32_t nnodes = 0, ntris = 0;
+  const int L = a.sc.L;
+  const bool closest = depth <= a.cam.D;
+  const bool shadows = depth >= 1;
+  const int q = depth & 1;
+  const int sp = (depth + 1) & 1;  // parity of depth - 1
+  const uint32_t nc = closest ? (depth == 0 ? uint32_t(a.path_count) : a.ctr->refl_count[depth]) : 0u;
+  const uint32_t nc_pad = round64(nc);
+  uint32_t total = nc_pad;
+  if (shadows)
+    for (int l = 0; l < L; ++l) total += round64(a.ctr->shadow_count[depth - 1][l]);
+  uint32_t c_nodes = 0, c_tris = 0, s_nodes = 0, s_tris = 0;
   while (true) {
     uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(&a.ctr->any_work[depth], 64u);
+    if (lane == 0) base = atomicAdd(&a.ctr->trace_work[depth], 64u);
     base = __shfl(base, 0);
     if (base >= total) break;
-    const uint32_t e = base + lane;
-    if (e < total) {
-      const float4 so = a.so[e], sd = a.sd[e];
-      const bool occ = any_hit<COUNT>(a.sc, f3(so), f3(sd), kSecondaryTmin, so.w, __float_as_int(sd.w),
-                                      a.brute != 0, st, nnodes, ntris);
-      a.vis[e] = occ ? 0 : 1;
+    if (base < nc_pad) {
+      // ---- closest-hit batch
+      const uint32_t e = base + lane;
+      if (e < nc) {
+        float3 o, d;
+        int exclude = -1;
+        bool valid = true;
+        if (depth == 0) {
+          int eye, x, y;
+          const int64_t p = a.path_begin + e;
+          valid = path_pixel(a.cam, p, &eye, &x, &y);
+          if (valid) {
+            primary_ray(a.cam, eye, x, y, &o, &d);
+            a.ro[q][e] = make_float4(o.x, o.y, o.z, __int_as_float(int(p)));
+            a.rd[q][e] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
+          } else {
+            a.ro[q][e] = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+          }
+        } else {
+          const float4 ro = a.ro[q][e], rd = a.rd[q][e];
+          o = f3(ro);
+          d = f3(rd);
+          exclude = __float_as_int(rd.w);
+        }
+        if (valid) {
+          Best b{INFINITY, -1, 0x7fffffff};
+          traverse<false, COUNT>(a.sc, o, d, depth == 0 ? 0.0f : kSecondaryTmin, exclude, a.brute != 0, b, st,
+                                 c_nodes, c_tris);
+          a.hit[e] = make_float2(b.t, __int_as_float(b.key));
+        }
+      }
+    } else {
+      // ---- shadow batch: find the light whose (64-aligned) range holds this batch
+      uint32_t start = nc_pad;
+      int l = 0;
+      uint32_t cnt = a.ctr->shadow_count[depth - 1][0];
+      while (l + 1 < L && base >= start + round64(cnt)) {
+        start += round64(cnt);
+        ++l;
+        cnt = a.ctr->shadow_count[depth - 1][l];
+      }
+      const uint32_t i = base - start + lane;
+      if (i < cnt) {
+        const size_t slot = size_t(l) * a.cap + i;
+        const float4 rec = a.srec[sp][slot];
+        const uint32_t owner = a.sowner[sp][slot];
+        const float3 P = f3(rec);
+        const float3 Lv = f3(a.sc.lights[2 * l]) - P;
+        const float dist = sqrtf(dot(Lv, Lv));
+        const float3 Ld = (1.0f / dist) * Lv;
+        Best b{dist, -1, 0};
+        traverse<true, COUNT>(a.sc, P, Ld, kSecondaryTmin, __float_as_int(rec.w), a.brute != 0, b, st, s_nodes,
+                              s_tris);
+        a.vis[sp][size_t(owner) * L + l] = b.key < 0 ? 1 : 0;
+      }
     }
   }
-  if (st.overflow) atomicOr(&a.ctr->pad[1], 1u);
+  if (st.overflow) atomicOr(&a.ctr->error, 1u);
   if (COUNT) {
-    add_work(a.ctr, 2, nnodes);
-    add_work(a.ctr, 3, ntris);
+    add_work(a.ctr, 0, c_nodes);
+    add_work(a.ctr, 1, c_tris);
+    add_work(a.ctr, 2, s_nodes);
+    add_work(a.ctr, 3, s_tris);
   }
 }
 
@@ -514,30 +465,25 @@ __device__ inline int32_t out_id(const DevScene& sc, int key) {
   return key;
 }
 
-// Exclusive prefix sum over the wave; *total gets the wave sum.
-__device__ inline uint32_t wave_exclusive_scan(uint32_t v, uint32_t* total) {
-  const int lane = lane_id();
-  uint32_t x = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    uint32_t y = __shfl_up(x, off);
-    if (lane >= off) x += y;
-  }
-  *total = __shfl(x, 63);
-  return x - v;
-}
+// ---------------------------------------------------------------------------------------------
+// k_shade: one thread per hit of depth `depth`.  Each block takes 256 consecutive entries per
+// iteration; new shadow records (one queue per light) and mirror rays are compacted with wave
+// ballots, a block prefix over the waves and one atomic per block and queue.
+// ---------------------------------------------------------------------------------------------
 
 template <bool PATH_IDS>
 __global__ __launch_bounds__(kBlock) void k_shade(KArgs a, int depth) {
-  const int lane = lane_id();
+  __shared__ uint32_t wcnt[kWaves][RT_MAX_LIGHTS + 1];
+  __shared__ uint32_t bbase[RT_MAX_LIGHTS + 1];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int q = depth & 1, nq = (depth + 1) & 1;
   const uint32_t total = depth == 0 ? uint32_t(a.path_count) : a.ctr->refl_count[depth];
   const int L = a.sc.L;
   const bool may_reflect = depth < a.cam.D;
-  const int64_t HW = int64_t(a.cam.W) * a.cam.H;
   const int D1 = a.cam.D + 1;
   uint32_t n_primary = 0;
-  for (uint32_t base = (blockIdx.x * kBlock + (threadIdx.x & ~63u)); base < total; base += gridDim.x * kBlock) {
-    const uint32_t e = base + lane;
+  for (uint32_t base = blockIdx.x * kBlock; base < total; base += gridDim.x * kBlock) {  // block-uniform loop
+    const uint32_t e = base + threadIdx.x;
     bool active = e < total;
     float4 ro = make_float4(0.f, 0.f, 0.f, __int_as_float(-1)), rd = make_float4(0.f, 0.f, 0.f, 0.f);
     float3 thr = make_float3(1.f, 1.f, 1.f);
@@ -546,25 +492,23 @@ __global__ __launch_bounds__(kBlock) void k_shade(KArgs a, int depth) {
       ro = a.ro[q][e];
       if (__float_as_int(ro.w) < 0) {
         active = false;
+        a.resinfo[q][e] = make_uint2(0xffffffffu, 0u);
       } else {
         rd = a.rd[q][e];
         hit = a.hit[e];
         if (depth > 0) thr = f3(a.thr[q][e]);
       }
     }
-    int eye = 0, x = 0, y = 0;
-    int64_t pix = 0;
-    float* rad = nullptr;
     uint32_t mask = 0;
     bool spawn = false;
     float3 P = make_float3(0.f, 0.f, 0.f), N = P, V = P, rdir = P, kr3 = P;
     float4 m0 = make_float4(0.f, 0.f, 0.f, 0.f), m1 = m0;
-    int key = -1;
+    const int key = __float_as_int(hit.y);
     if (active) {
+      int eye, x, y;
       path_pixel(a.cam, int64_t(__float_as_int(ro.w)), &eye, &x, &y);
-      pix = int64_t(y) * a.cam.W + x;
-      rad = a.radiance[eye] + 3 * pix;
-      key = __float_as_int(hit.y);
+      const int64_t pix = int64_t(y) * a.cam.W + x;
+      float* rad = a.radiance[eye] + 3 * pix;
       const float3 o = f3(ro), d = f3(rd);
       if (depth == 0) {
         ++n_primary;
@@ -608,18 +552,31 @@ __global__ __launch_bounds__(kBlock) void k_shade(KArgs a, int depth) {
         rad[1] += add.y;
         rad[2] += add.z;
       }
+      a.resinfo[q][e] = make_uint2(uint32_t(__float_as_int(ro.w)), mask);
     }
-    // compact shadow records
-    uint32_t nsh = __popc(mask), wave_total;
-    const uint32_t excl = wave_exclusive_scan(nsh, &wave_total);
-    uint32_t sbase = 0;
-    if (lane == 0 && wave_total) sbase = atomicAdd(&a.ctr->shadow_count[depth], wave_total);
-    sbase = __shfl(sbase, 0) + excl;
-    if (active) {
-      a.resinfo[e] = make_uint2(sbase, mask);
-      uint32_t k = sbase;
-      for (int l = 0; l < L; ++l) {
-        if (!(mask >> l & 1u)) continue;
+    // per-wave counts of every queue, then one atomic per block and queue
+    for (int l = 0; l <= L; ++l) {
+      const uint64_t bal = __ballot(l < L ? ((mask >> l) & 1u) != 0 : spawn);
+      if (lane == 0) wcnt[wave][l] = uint32_t(__popcll(bal));
+    }
+    __syncthreads();
+    if (threadIdx.x <= uint32_t(L)) {
+      const int l = threadIdx.x;
+      uint32_t run = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = wcnt[w][l];
+        wcnt[w][l] = run;
+        run += c;
+      }
+      uint32_t* ctr = l < L ? &a.ctr->shadow_count[depth][l] : &a.ctr->refl_count[depth + 1];
+      bbase[l] = run ? atomicAdd(ctr, run) : 0u;
+    }
+    __syncthreads();
+    for (int l = 0; l < L; ++l) {
+      const bool mine = ((mask >> l) & 1u) != 0;
+      const uint64_t bal = __ballot(mine);
+      if (mine) {
+        const uint32_t slot = bbase[l] + wcnt[wave][l] + uint32_t(__popcll(bal & lanemask_lt()));
         const float3 Lv = f3(a.sc.lights[2 * l]) - P;
         const float dist = sqrtf(dot(Lv, Lv));
         const float3 Ld = (1.0f / dist) * Lv;
@@ -629,32 +586,30 @@ __global__ __launch_bounds__(kBlock) void k_shade(KArgs a, int depth) {
         const float spec = powf(rv, m0.w);
         const float3 I = f3(a.sc.lights[2 * l + 1]);
         const float3 term = mul(I, ndl * f3(m0) + spec * f3(m1));
-        a.so[k] = make_float4(P.x, P.y, P.z, dist);
-        a.sd[k] = make_float4(Ld.x, Ld.y, Ld.z, __int_as_float(key));
-        a.contrib[k] = make_float4(term.x * thr.x, term.y * thr.y, term.z * thr.z, 0.f);
-        ++k;
+        const size_t s = size_t(l) * a.cap + slot;
+        a.srec[q][s] = make_float4(P.x, P.y, P.z, __int_as_float(key));
+        a.sowner[q][s] = e;
+        a.contrib[q][size_t(e) * L + l] = make_float4(term.x * thr.x, term.y * thr.y, term.z * thr.z, 0.f);
       }
     }
-    // compact mirror rays into the next queue
-    const uint64_t bal = __ballot(spawn);
-    if (may_reflect && bal) {
-      uint32_t rbase = 0;
-      if (lane == 0) rbase = atomicAdd(&a.ctr->refl_count[depth + 1], uint32_t(__popcll(bal)));
-      rbase = __shfl(rbase, 0);
+    if (may_reflect) {
+      const uint64_t bal = __ballot(spawn);
       if (spawn) {
-        const uint32_t slot = rbase + uint32_t(__popcll(bal & lanemask_lt()));
+        const uint32_t slot = bbase[L] + wcnt[wave][L] + uint32_t(__popcll(bal & lanemask_lt()));
         a.ro[nq][slot] = make_float4(P.x, P.y, P.z, ro.w);
         a.rd[nq][slot] = make_float4(rdir.x, rdir.y, rdir.z, __int_as_float(key));
         a.thr[nq][slot] = make_float4(thr.x * kr3.x, thr.y * kr3.y, thr.z * kr3.z, 0.f);
       }
     }
+    __syncthreads();  // wcnt / bbase are reused by the next iteration
   }
   if (depth == 0) {
     for (int off = 32; off > 0; off >>= 1) n_primary += __shfl_xor(n_primary, off);
-    if (lane == 0 && n_primary) atomicAdd(&a.ctr->pad[0], n_primary);
+    if (lane == 0 && n_primary) atomicAdd(&a.ctr->primary, n_primary);
   }
 }
 
+// k_resolve: adds the unoccluded lights' terms of depth `depth` to each path's pixel, in light order.
 template <bool PATH_IDS>
 __global__ __launch_bounds__(kBlock) void k_resolve(KArgs a, int depth) {
   const int q = depth & 1;
@@ -662,31 +617,23 @@ __global__ __launch_bounds__(kBlock) void k_resolve(KArgs a, int depth) {
   const int L = a.sc.L;
   const int D1 = a.cam.D + 1;
   for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < total; e += gridDim.x * kBlock) {
-    const int path = __float_as_int(a.ro[q][e].w);
-    if (path < 0) continue;
-    const uint2 ri = a.resinfo[e];
-    if (ri.y == 0 && !PATH_IDS) continue;
+    const uint2 ri = a.resinfo[q][e];
+    if (ri.y == 0) continue;  // no shadow rays (also invalid paths)
     int eye, x, y;
-    path_pixel(a.cam, path, &eye, &x, &y);
+    path_pixel(a.cam, int64_t(ri.x), &eye, &x, &y);
     const int64_t pix = int64_t(y) * a.cam.W + x;
     float3 sum = make_float3(0.f, 0.f, 0.f);
-    uint32_t k = ri.x;
     for (int l = 0; l < L; ++l) {
-      uint8_t state = 0;
-      if (ri.y >> l & 1u) {
-        const bool v = a.vis[k] != 0;
-        if (v) sum = sum + f3(a.contrib[k]);
-        state = v ? 2 : 1;
-        ++k;
-      }
-      if (PATH_IDS) a.shadow_state[eye][(pix * D1 + depth) * L + l] = state;
+      if (!((ri.y >> l) & 1u)) continue;
+      const size_t k = size_t(e) * L + l;
+      const bool v = a.vis[q][k] != 0;
+      if (v) sum = sum + f3(a.contrib[q][k]);
+      if (PATH_IDS) a.shadow_state[eye][(pix * D1 + depth) * L + l] = v ? 2 : 1;
     }
-    if (ri.y) {
-      float* rad = a.radiance[eye] + 3 * pix;
-      rad[0] += sum.x;
-      rad[1] += sum.y;
-      rad[2] += sum.z;
-    }
+    float* rad = a.radiance[eye] + 3 * pix;
+    rad[0] += sum.x;
+    rad[1] += sum.y;
+    rad[2] += sum.z;
   }
 }
 
@@ -695,19 +642,20 @@ __global__ void k_reset(Counters* ctr) {
   for (int i = threadIdx.x; i < int(sizeof(Counters) / 4); i += blockDim.x) p[i] = 0;
 }
 
-__global__ void k_finish(const Counters* ctr, int D, int64_t* out) {
+__global__ void k_finish(const Counters* ctr, int D, int L, int64_t* out) {
   if (threadIdx.x != 0) return;
   int64_t refl = 0, shadow = 0;
   for (int d = 1; d <= D; ++d) refl += ctr->refl_count[d];
-  for (int d = 0; d <= D; ++d) shadow += ctr->shadow_count[d];
-  out[RT_COUNT_PRIMARY] += ctr->pad[0];
+  for (int d = 0; d <= D; ++d)
+    for (int l = 0; l < L; ++l) shadow += ctr->shadow_count[d][l];
+  out[RT_COUNT_PRIMARY] += ctr->primary;
   out[RT_COUNT_REFLECTION] += refl;
   out[RT_COUNT_SHADOW] += shadow;
   out[RT_COUNT_CLOSEST_NODES] += int64_t(ctr->work[0]);
   out[RT_COUNT_CLOSEST_TRIS] += int64_t(ctr->work[1]);
   out[RT_COUNT_ANY_NODES] += int64_t(ctr->work[2]);
   out[RT_COUNT_ANY_TRIS] += int64_t(ctr->work[3]);
-  out[RT_COUNT_ERRORS] += ctr->pad[1];
+  out[RT_COUNT_ERRORS] += ctr->error;
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -731,8 +679,7 @@ int trace_grid_size(int device) {
   int grid = kMaxTraceBlocks;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_closest<false, false>, kBlock, 0) != hipSuccess ||
-        per_cu <= 0)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<false>, kBlock, 0) != hipSuccess || per_cu <= 0)
       per_cu = 4;
     grid = std::min(kMaxTraceBlocks, prop.multiProcessorCount * per_cu);
   }
@@ -751,18 +698,18 @@ size_t plan_render(int64_t chunk, int32_t L, int grid_trace, RenderPlan* p) {
   const size_t ns = n * size_t(std::max(L, 1));
   p->chunk_paths = chunk;
   p->grid_trace = grid_trace;
-  p->counters_off = take(sizeof(Counters) + 64);
+  p->counters_off = take(sizeof(Counters));
   for (int k = 0; k < 2; ++k) {
     p->ro_off[k] = take(n * 16);
     p->rd_off[k] = take(n * 16);
     p->thr_off[k] = take(n * 16);
+    p->resinfo_off[k] = take(n * 8);
+    p->srec_off[k] = take(ns * 16);
+    p->sowner_off[k] = take(ns * 4);
+    p->contrib_off[k] = take(ns * 16);
+    p->vis_off[k] = take(ns);
   }
   p->hit_off = take(n * 8);
-  p->resinfo_off = take(n * 8);
-  p->so_off = take(ns * 16);
-  p->sd_off = take(ns * 16);
-  p->contrib_off = take(ns * 16);
-  p->vis_off = take(ns);
   p->gstack_off = take(size_t(kMaxTraceBlocks) * kBlock * kStackGlobal * 4);
   p->bytes = off;
   return off;
@@ -779,13 +726,13 @@ hipError_t render_chunk(const RenderArgs& ra, hipStream_t s, TimerImpl* timer) {
     a.ro[k] = reinterpret_cast<float4*>(ws + p.ro_off[k]);
     a.rd[k] = reinterpret_cast<float4*>(ws + p.rd_off[k]);
     a.thr[k] = reinterpret_cast<float4*>(ws + p.thr_off[k]);
+    a.resinfo[k] = reinterpret_cast<uint2*>(ws + p.resinfo_off[k]);
+    a.srec[k] = reinterpret_cast<float4*>(ws + p.srec_off[k]);
+    a.sowner[k] = reinterpret_cast<uint32_t*>(ws + p.sowner_off[k]);
+    a.contrib[k] = reinterpret_cast<float4*>(ws + p.contrib_off[k]);
+    a.vis[k] = reinterpret_cast<uint8_t*>(ws + p.vis_off[k]);
   }
   a.hit = reinterpret_cast<float2*>(ws + p.hit_off);
-  a.resinfo = reinterpret_cast<uint2*>(ws + p.resinfo_off);
-  a.so = reinterpret_cast<float4*>(ws + p.so_off);
-  a.sd = reinterpret_cast<float4*>(ws + p.sd_off);
-  a.contrib = reinterpret_cast<float4*>(ws + p.contrib_off);
-  a.vis = reinterpret_cast<uint8_t*>(ws + p.vis_off);
   a.gstack = reinterpret_cast<uint32_t*>(ws + p.gstack_off);
   const rt_stereo_output* o = ra.out;
   const bool ids = (ra.flags & RT_FLAG_PATH_IDS) && o->path_prims[0] && o->path_prims[1] && o->shadow_state[0] &&
@@ -800,6 +747,7 @@ hipError_t render_chunk(const RenderArgs& ra, hipStream_t s, TimerImpl* timer) {
   }
   a.path_begin = ra.path_begin;
   a.path_count = ra.path_count;
+  a.cap = uint32_t(p.chunk_paths);
   a.brute = (ra.flags & RT_FLAG_BRUTE_FORCE) ? 1 : 0;
   a.trace_threads = p.grid_trace * kBlock;
 
@@ -811,26 +759,24 @@ hipError_t render_chunk(const RenderArgs& ra, hipStream_t s, TimerImpl* timer) {
   e = hipGetLastError();
   if (timer) timer_end(timer, RT_STAGE_SETUP, s);
   if (e != hipSuccess) return e;
-  for (int d = 0; d <= a.cam.D; ++d) {
-    if (d == 0)
-      e = count ? launch(k_closest<true, true>, gtrace, a, d, s, timer, RT_STAGE_TRACE_CLOSEST)
-                : launch(k_closest<true, false>, gtrace, a, d, s, timer, RT_STAGE_TRACE_CLOSEST);
-    else
-      e = count ? launch(k_closest<false, true>, gtrace, a, d, s, timer, RT_STAGE_TRACE_CLOSEST)
-                : launch(k_closest<false, false>, gtrace, a, d, s, timer, RT_STAGE_TRACE_CLOSEST);
+  const int D = a.cam.D;
+  for (int d = 0; d <= D + 1; ++d) {
+    e = count ? launch(k_trace<true>, gtrace, a, d, s, timer, RT_STAGE_TRACE)
+              : launch(k_trace<false>, gtrace, a, d, s, timer, RT_STAGE_TRACE);
     if (e != hipSuccess) return e;
-    e = ids ? launch(k_shade<true>, gstream, a, d, s, timer, RT_STAGE_SHADE)
-            : launch(k_shade<false>, gstream, a, d, s, timer, RT_STAGE_SHADE);
-    if (e != hipSuccess) return e;
-    e = count ? launch(k_any<true>, gtrace, a, d, s, timer, RT_STAGE_TRACE_ANY)
-              : launch(k_any<false>, gtrace, a, d, s, timer, RT_STAGE_TRACE_ANY);
-    if (e != hipSuccess) return e;
-    e = ids ? launch(k_resolve<true>, gstream, a, d, s, timer, RT_STAGE_RESOLVE)
-            : launch(k_resolve<false>, gstream, a, d, s, timer, RT_STAGE_RESOLVE);
-    if (e != hipSuccess) return e;
+    if (d <= D) {
+      e = ids ? launch(k_shade<true>, gstream, a, d, s, timer, RT_STAGE_SHADE)
+              : launch(k_shade<false>, gstream, a, d, s, timer, RT_STAGE_SHADE);
+      if (e != hipSuccess) return e;
+    }
+    if (d >= 1) {
+      e = ids ? launch(k_resolve<true>, gstream, a, d - 1, s, timer, RT_STAGE_RESOLVE)
+              : launch(k_resolve<false>, gstream, a, d - 1, s, timer, RT_STAGE_RESOLVE);
+      if (e != hipSuccess) return e;
+    }
   }
   if (o->ray_counts) {
-    k_finish<<<1, 64, 0, s>>>(a.ctr, a.cam.D, o->ray_counts);
+    k_finish<<<1, 64, 0, s>>>(a.ctr, D, a.sc.L, o->ray_counts);
     e = hipGetLastError();
   }
   return e;

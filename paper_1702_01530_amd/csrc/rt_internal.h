@@ -62,14 +62,14 @@ struct DevCamera {
   int32_t tiles_x, tiles_y;
 };
 
-// Work counters inside the render workspace (uint32 slots unless noted).
+// Work counters inside the render workspace.
 struct Counters {
-  uint32_t refl_count[RT_MAX_DEPTH + 2];    // entries of the mirror-ray queue at depth d
-  uint32_t shadow_count[RT_MAX_DEPTH + 2];  // shadow records emitted at depth d
-  uint32_t closest_work[RT_MAX_DEPTH + 2];  // persistent work cursor of the closest-hit launch at depth d
-  uint32_t any_work[RT_MAX_DEPTH + 2];      // persistent work cursor of the shadow launch at depth d
-  unsigned long long work[4];               // node visits / tri tests (closest, any)
-  uint32_t pad[16];
+  uint32_t refl_count[RT_MAX_DEPTH + 2];                   // entries of the mirror-ray queue at depth d
+  uint32_t shadow_count[RT_MAX_DEPTH + 2][RT_MAX_LIGHTS];  // shadow records of depth d towards light l
+  uint32_t trace_work[RT_MAX_DEPTH + 2];                   // persistent work cursor of the trace launch d
+  uint32_t primary;                                        // valid primary paths
+  uint32_t error;                                          // consistency-check hits
+  unsigned long long work[4];                              // node visits / tri tests (closest, shadow)
 };
 
 // Tile order of paths: a tile of 8x8 pixels of the left eye, then the same tile of the right eye.
@@ -95,6 +95,7 @@ struct BuildPlan {
 };
 
 BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool bvh);
+int leaf_size();  // largest number of triangles the build puts in one leaf (1..kLeafMaxTris)
 
 struct BuildResult {
   uint32_t status_bits;  // 1 non-finite vertex, 2 triangle material out of range, 4 sphere, 8 plane
@@ -111,8 +112,8 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
 
 struct RenderPlan {
   int64_t chunk_paths;  // paths per pass (multiple of kPathsPerTile)
-  size_t counters_off, ro_off[2], rd_off[2], thr_off[2], hit_off, resinfo_off, so_off, sd_off, contrib_off,
-      vis_off, gstack_off;
+  size_t counters_off, ro_off[2], rd_off[2], thr_off[2], hit_off, resinfo_off[2], srec_off[2], sowner_off[2],
+      contrib_off[2], vis_off[2], gstack_off;
   size_t bytes;
   int grid_trace;  // persistent workgroups for the traversal kernels
 };

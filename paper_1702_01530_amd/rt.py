@@ -25,7 +25,7 @@ RT_MAX_LIGHTS, RT_MAX_DEPTH = 8, 8
 RT_NUM_COUNTERS = 8
 COUNTER_NAMES = ["primary", "reflection", "shadow", "closest_nodes", "closest_tris", "any_nodes", "any_tris", "errors"]
 RT_NUM_STAGES = 8
-STAGE_NAMES = ["trace_closest", "trace_any", "shade", "resolve", "setup", "readback"]
+STAGE_NAMES = ["trace", "shade", "resolve", "setup", "readback"]
 
 
 class RtError(RuntimeError):

@@ -168,7 +168,8 @@ def test_pinned_readback_and_timer(torch_cuda):
     torch.cuda.synchronize()
     assert torch.equal(out["host_radiance"], out["radiance"].cpu())
     t = timer.read()
-    assert t["trace_closest"][1] == cam.max_depth + 1 and t["trace_closest"][0] > 0
+    assert t["trace"][1] == cam.max_depth + 2 and t["trace"][0] > 0
+    assert t["shade"][1] == cam.max_depth + 1 and t["resolve"][1] == cam.max_depth + 1
     assert t["readback"][1] == 1 and t["readback"][0] > 0
     timer.close()
     gs.close()
