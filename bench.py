@@ -30,6 +30,20 @@ CLOSEST_RAY_IO = 32 + 8   # ray in (origin+path, direction+exclude) + hit out (t
 ANY_RAY_IO = 32 + 1       # shadow record in + visibility byte out
 
 
+def measured_traffic(workload_name: str):
+    """HBM bytes per k_trace launch from the committed rocprofv3 counter runs, if the kernel sources
+    are still the ones that were profiled (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_trace_{workload_name}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    h = hashlib.sha256()
+    for src in t["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return t["hbm_bytes_per_launch"] if h.hexdigest() == t["sources_sha256"] else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -215,7 +229,7 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": "k_trace",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
             "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms,
             "launches_per_frame": launches_per_frame,
             "bytes_per_frame": {"closest": int(closest_bytes), "shadow": int(any_bytes)},
