@@ -324,7 +324,9 @@ rt_status rt_scene_build(const rt_scene_desc* desc, void* storage, size_t storag
   if (res.status_bits & 8u)
     return fail(RT_ERR_INVALID_ARGUMENT, "a plane is not finite, has a zero normal or a material out of range");
   if (res.status_bits & 16u) return fail(RT_ERR_DEVICE, "internal error: inconsistent BVH hierarchy");
-  if (res.depth > 96) return fail(RT_ERR_UNSUPPORTED, "BVH depth %d exceeds the traversal stack", res.depth);
+  // the traversal stack holds at most (width - 1) entries per level of the tree
+  if ((srt::kNodeWidth - 1) * res.depth >= srt::kStackMax)
+    return fail(RT_ERR_UNSUPPORTED, "BVH depth %d exceeds the traversal stack", res.depth);
 
   rt_scene_s* h = new (std::nothrow) rt_scene_s();
   if (!h) return fail(RT_ERR_DEVICE, "out of host memory");
@@ -359,7 +361,7 @@ rt_status rt_scene_build(const rt_scene_desc* desc, void* storage, size_t storag
   info.bvh_depth = plan.bvh ? res.depth : 0;
   info.leaf_size = desc->num_triangles > 0 ? (plan.bvh ? srt::leaf_size() : 1) : 0;
   info.num_nodes = res.num_nodes;
-  info.node_bytes = res.num_nodes * 64;
+  info.node_bytes = res.num_nodes * srt::kNodeBytes;
   info.triangle_bytes = desc->num_triangles * 48;
   for (int k = 0; k < 3; ++k) {
     info.bounds_lo[k] = res.lo[k];

@@ -228,7 +228,8 @@ __global__ __launch_bounds__(kBlock) void k_digit_hist(const uint64_t* __restric
 }
 
 // Exclusive scan of hist (length m) in place, one block.
-__global__ __launch_bounds__(1024) void k_scan_exclusive(uint32_t* __restrict__ data, int64_t m) {
+__global__ __launch_bounds__(1024) void k_scan_exclusive(uint32_t* __restrict__ data, int64_t m,
+                                                          uint32_t* __restrict__ total_out) {
   __shared__ uint32_t part[1024];
   const int tid = threadIdx.x;
   int64_t per = (m + 1023) / 1024;
@@ -249,6 +250,7 @@ __global__ __launch_bounds__(1024) void k_scan_exclusive(uint32_t* __restrict__ 
     data[i] = run;
     run += x;
   }
+  if (total_out && tid == 1023) *total_out = part[1023];
 }
 
 __device__ inline uint64_t lanemask_lt() {
@@ -453,6 +455,128 @@ __global__ __launch_bounds__(kBlock) void k_pack_nodes(PackArgs a) {
   out[3] = make_float4(__int_as_float(child_ref(a, ch.x)), __int_as_float(child_ref(a, ch.y)), 0.f, 0.f);
 }
 
+// ---------------------------------------------------------------------------------------------
+// 7b. Collapse into a 4-wide BVH, top-down one level at a time.  A BVH4 node takes a BVH2 node's two
+// children and, while it has fewer than four, replaces its largest-area internal child by that
+// child's two children (keeping left-to-right order).  Internal children become the next level's
+// nodes; their indices come from a prefix sum, so the layout is deterministic and each level's
+// nodes are contiguous.
+// ---------------------------------------------------------------------------------------------
+
+constexpr int kWideEmpty = INT32_MIN;
+
+struct WideArgs {
+  const int2* children;
+  const float4* nodebox;
+  const float4* leaf_lo;
+  const float4* leaf_hi;
+  const uint32_t* sorted_ids;
+  const int2* frontier;  // (BVH2 node, BVH4 index)
+  int64_t m;
+  int4* sel;             // chosen BVH2 references per frontier item
+  uint32_t* nint;        // internal children per item -> exclusive offsets (+ total at [m])
+  int2* next;            // next frontier
+  float4* nodes;         // 8 float4 per BVH4 node
+  int64_t level_base;    // BVH4 index of the next level's first node
+  float pad;
+};
+
+__device__ inline float half_area(float4 lo, float4 hi) {
+  const float dx = hi.x - lo.x, dy = hi.y - lo.y, dz = hi.z - lo.z;
+  return dx * dy + dy * dz + dz * dx;
+}
+
+__global__ __launch_bounds__(kBlock) void k_wide_select(WideArgs a) {
+  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= a.m) return;
+  const int2 ch = a.children[a.frontier[i].x];
+  int r[4] = {ch.x, ch.y, kWideEmpty, kWideEmpty};
+  int cnt = 2;
+  for (int step = 0; step < 2; ++step) {
+    int best = -1;
+    float best_area = -1.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k < cnt && r[k] >= 0) {
+        const float ar = half_area(a.nodebox[2 * r[k]], a.nodebox[2 * r[k] + 1]);
+        if (ar > best_area) {
+          best_area = ar;
+          best = k;
+        }
+      }
+    }
+    if (best < 0) break;
+    const int2 c = a.children[r[best]];
+    // insert c.y after position best, shifting the tail right
+#pragma unroll
+    for (int k = 3; k > 0; --k)
+      if (k > best + 1 && k <= cnt) r[k] = r[k - 1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k == best) r[k] = c.x;
+      if (k == best + 1) r[k] = c.y;
+    }
+    ++cnt;
+  }
+  a.sel[i] = make_int4(r[0], r[1], r[2], r[3]);
+  uint32_t n = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) n += (r[k] >= 0) ? 1u : 0u;
+  a.nint[i] = n;
+}
+
+__global__ __launch_bounds__(kBlock) void k_wide_emit(WideArgs a) {
+  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= a.m) return;
+  const int b4 = a.frontier[i].y;
+  const int4 s4 = a.sel[i];
+  const int r[4] = {s4.x, s4.y, s4.z, s4.w};
+  const uint32_t off = a.nint[i];
+  float lo[3][4], hi[3][4];
+  int ref[4];
+  uint32_t k_int = 0;
+  const float p = a.pad;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    float4 l, h;
+    if (r[k] == kWideEmpty) {
+      // an empty slot: a box at +inf on every axis misses every ray in the slab test
+      l = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+      h = l;
+      ref[k] = 0;
+    } else if (r[k] < 0) {
+      const uint32_t id = a.sorted_ids[~r[k]];
+      l = a.leaf_lo[id];
+      h = a.leaf_hi[id];
+      l = make_float4(l.x - p, l.y - p, l.z - p, 0.f);
+      h = make_float4(h.x + p, h.y + p, h.z + p, 0.f);
+      ref[k] = ~((~r[k]) << 2);
+    } else {
+      l = a.nodebox[2 * r[k]];
+      h = a.nodebox[2 * r[k] + 1];
+      l = make_float4(l.x - p, l.y - p, l.z - p, 0.f);
+      h = make_float4(h.x + p, h.y + p, h.z + p, 0.f);
+      const int idx = int(a.level_base + off + k_int);
+      a.next[off + k_int] = make_int2(r[k], idx);
+      ++k_int;
+      ref[k] = idx;
+    }
+    lo[0][k] = l.x, lo[1][k] = l.y, lo[2][k] = l.z;
+    hi[0][k] = h.x, hi[1][k] = h.y, hi[2][k] = h.z;
+  }
+  float4* out = a.nodes + 8 * int64_t(b4);
+  out[0] = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
+  out[1] = make_float4(hi[0][0], hi[0][1], hi[0][2], hi[0][3]);
+  out[2] = make_float4(lo[1][0], lo[1][1], lo[1][2], lo[1][3]);
+  out[3] = make_float4(hi[1][0], hi[1][1], hi[1][2], hi[1][3]);
+  out[4] = make_float4(lo[2][0], lo[2][1], lo[2][2], lo[2][3]);
+  out[5] = make_float4(hi[2][0], hi[2][1], hi[2][2], hi[2][3]);
+  out[6] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), __int_as_float(ref[2]), __int_as_float(ref[3]));
+  out[7] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__global__ void k_set_int2(int2* p, int2 v) { *p = v; }
+
 __global__ __launch_bounds__(kBlock) void k_pack_tris(const float* __restrict__ tris, const uint32_t* __restrict__ mat,
                                                       const uint32_t* __restrict__ order, int64_t T,
                                                       float4* __restrict__ recs) {
@@ -486,8 +610,8 @@ BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool
     off = align256(off + bytes);
     return o;
   };
-  int64_t num_nodes = p.bvh ? T - 1 : 0;
-  p.nodes_off = take(size_t(num_nodes) * 64);
+  int64_t num_nodes = p.bvh ? T - 1 : 0;  // an upper bound for the 4-wide tree
+  p.nodes_off = take(size_t(num_nodes) * kNodeBytes);
   p.tris_off = take(size_t(T) * 48);
   p.spheres_off = take(size_t(S) * 16);
   p.sphere_mat_off = take(size_t(S) * 4);
@@ -517,6 +641,10 @@ BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool
     p.parent_off = take(size_t(2 * T) * 4);
     p.flags_off = take(size_t(T) * 4);
     p.nodebox_off = take(size_t(T) * 32);
+    p.frontier_off[0] = take(size_t(T) * 8);
+    p.frontier_off[1] = take(size_t(T) * 8);
+    p.sel_off = take(size_t(T) * 16);
+    p.nint_off = take(size_t(T + 1) * 4);
   }
   p.scratch_bytes = off;
   return p;
@@ -615,7 +743,7 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
         int shift = pass * kRadixBits;
         k_digit_hist<<<unsigned(nb), kBlock, 0, stream>>>(k0, T, shift, hist, nb);
         SRT_LAUNCH_CHECK();
-        k_scan_exclusive<<<1, 1024, 0, stream>>>(hist, nb * kRadix);
+        k_scan_exclusive<<<1, 1024, 0, stream>>>(hist, nb * kRadix, nullptr);
         SRT_LAUNCH_CHECK();
         k_scatter<<<unsigned(nb), kBlock, 0, stream>>>(k0, i0, T, shift, hist, nb, k1, i1);
         SRT_LAUNCH_CHECK();
@@ -652,11 +780,51 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
       pa.n = T;
       pa.pad = m * 0x1p-18f + 1e-20f;  // conservative box growth (slab and triangle-test rounding)
       pa.leaf_size = SRT_LEAF_SIZE;
-      k_pack_nodes<<<blocks_for(T - 1), kBlock, 0, stream>>>(pa);
-      SRT_LAUNCH_CHECK();
+      if (kNodeWidth == 2) {
+        k_pack_nodes<<<blocks_for(T - 1), kBlock, 0, stream>>>(pa);
+        SRT_LAUNCH_CHECK();
+        result->num_nodes = T - 1;
+      } else {
+        WideArgs wa;
+        wa.children = children;
+        wa.nodebox = nodebox;
+        wa.leaf_lo = lo;
+        wa.leaf_hi = hi;
+        wa.sorted_ids = i0;
+        wa.sel = reinterpret_cast<int4*>(scratch + plan.sel_off);
+        wa.nint = reinterpret_cast<uint32_t*>(scratch + plan.nint_off);
+        wa.nodes = pa.nodes;
+        wa.pad = pa.pad;
+        int2* fr[2] = {reinterpret_cast<int2*>(scratch + plan.frontier_off[0]),
+                       reinterpret_cast<int2*>(scratch + plan.frontier_off[1])};
+        k_set_int2<<<1, 1, 0, stream>>>(fr[0], make_int2(0, 0));
+        SRT_LAUNCH_CHECK();
+        int64_t m = 1, allocated = 1;
+        int levels = 0;
+        while (m > 0) {
+          wa.frontier = fr[levels & 1];
+          wa.next = fr[(levels + 1) & 1];
+          wa.m = m;
+          wa.level_base = allocated;
+          k_wide_select<<<blocks_for(m), kBlock, 0, stream>>>(wa);
+          SRT_LAUNCH_CHECK();
+          k_scan_exclusive<<<1, 1024, 0, stream>>>(wa.nint, m, wa.nint + m);
+          SRT_LAUNCH_CHECK();
+          k_wide_emit<<<blocks_for(m), kBlock, 0, stream>>>(wa);
+          SRT_LAUNCH_CHECK();
+          uint32_t next_m = 0;
+          SRT_CHECK(hipMemcpyAsync(&next_m, wa.nint + m, sizeof(next_m), hipMemcpyDeviceToHost, stream));
+          SRT_CHECK(hipStreamSynchronize(stream));
+          allocated += next_m;
+          m = next_m;
+          ++levels;
+          if (levels > 128 || allocated > T - 1) return hipErrorUnknown;  // impossible for a valid hierarchy
+        }
+        result->num_nodes = allocated;
+        depth = levels;
+      }
       k_pack_tris<<<blocks_for(T), kBlock, 0, stream>>>(desc->triangles, desc->tri_material, i0, T, recs);
       SRT_LAUNCH_CHECK();
-      result->num_nodes = T - 1;
       result->root = 0;
     } else {
       k_pack_tris<<<blocks_for(T), kBlock, 0, stream>>>(desc->triangles, desc->tri_material, nullptr, T, recs);

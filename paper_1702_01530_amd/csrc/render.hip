@@ -38,7 +38,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kStackLds = SRT_STACK_LDS;       // traversal stack entries per lane kept in LDS (power of two)
-constexpr int kStackGlobal = 96 - kStackLds;   // older entries spill to the workspace
+constexpr int kStackGlobal = kStackMax - kStackLds;  // older entries spill to the workspace
 constexpr int kMaxTraceBlocks = 2048;
 static_assert((kStackLds & (kStackLds - 1)) == 0, "LDS stack size must be a power of two");
 
@@ -207,7 +207,7 @@ struct Stack {
 
   __device__ inline void push(int v) {
     if (sp >= kStackLds) {
-      if (sp - kStackLds >= kStackGlobal) {  // cannot happen for trees of depth <= 97; never write out of bounds
+      if (sp - kStackLds >= kStackGlobal) {  // excluded by the build's depth check; never write out of bounds
         overflow = true;
         return;
       }
@@ -283,10 +283,11 @@ __device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tm
         st.overflow = true;
         return;
       }
-      const float4* n = sc.nodes + 4 * node;
-      const float4 a = n[0], b = n[1], c = n[2], e = n[3];
       if (COUNT) ++nnodes;
       const float tmax = limit();
+#if SRT_BVH_WIDTH == 2
+      const float4* n = sc.nodes + 4 * node;
+      const float4 a = n[0], b = n[1], c = n[2], e = n[3];
       const float t0 = slab(a.x, a.y, a.z, a.w, c.x, c.y, inv, oi, tmin, tmax);
       const float t1 = slab(b.x, b.y, b.z, b.w, c.z, c.w, inv, oi, tmin, tmax);
       const int c0 = __float_as_int(e.x), c1 = __float_as_int(e.y);
@@ -305,6 +306,37 @@ __device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tm
         node = c1;
         continue;
       }
+#else
+      const float4* n = sc.nodes + 8 * node;
+      const float4 lx = n[0], hx = n[1], ly = n[2], hy = n[3], lz = n[4], hz = n[5], cr = n[6];
+      float t[4] = {slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, inv, oi, tmin, tmax),
+                    slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, inv, oi, tmin, tmax),
+                    slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, inv, oi, tmin, tmax),
+                    slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, inv, oi, tmin, tmax)};
+      int r[4] = {__float_as_int(cr.x), __float_as_int(cr.y), __float_as_int(cr.z), __float_as_int(cr.w)};
+      // order the four children by entry distance (missed ones, at +inf, sort last)
+      auto cas = [&](int i, int j) {
+        const bool sw = t[j] < t[i];
+        const float ti = t[i], tj = t[j];
+        const int ri = r[i], rj = r[j];
+        t[i] = sw ? tj : ti;
+        t[j] = sw ? ti : tj;
+        r[i] = sw ? rj : ri;
+        r[j] = sw ? ri : rj;
+      };
+      cas(0, 1);
+      cas(2, 3);
+      cas(0, 2);
+      cas(1, 3);
+      cas(1, 2);
+      if (t[0] < INFINITY) {
+        if (t[3] < INFINITY) st.push(r[3]);
+        if (t[2] < INFINITY) st.push(r[2]);
+        if (t[1] < INFINITY) st.push(r[1]);
+        node = r[0];
+        continue;
+      }
+#endif
     } else {
       const int code = ~node;
       const int first = code >> 2, count = (code & 3) + 1;

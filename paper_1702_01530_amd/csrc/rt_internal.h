@@ -14,11 +14,15 @@ namespace srt {
 // Device scene view (passed by value as a kernel argument)
 // ---------------------------------------------------------------------------------------------
 //
-// BVH2 node, 64 bytes = 4 x float4:
+// BVH2 node (width 2), 64 bytes = 4 x float4:
 //   n[0] = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
 //   n[1] = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
 //   n[2] = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
 //   n[3] = (child0, child1, -, -) as int bits
+// BVH4 node (width 4), 128 bytes = 8 x float4, one lane per child:
+//   n[0..5] = lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of children 0..3
+//   n[6]    = child references as int bits;  n[7] unused
+//   an empty child slot has a box at +inf on every axis (never entered).
 // A child reference >= 0 is an internal node index; < 0 is a leaf ~(first << 2 | (count - 1)),
 // covering triangle records [first, first + count).
 //
@@ -30,13 +34,19 @@ namespace srt {
 // Primitive keys inside the kernels: triangle record index [0,T), sphere T+s, plane T+S+p.
 // Output ids are the input order (a record carries its original id).
 
+#ifndef SRT_BVH_WIDTH
+#define SRT_BVH_WIDTH 4
+#endif
+constexpr int kNodeWidth = SRT_BVH_WIDTH;        // 2: 64-byte BVH2 nodes; 4: 128-byte BVH4 nodes
+constexpr int kNodeFloat4 = kNodeWidth == 2 ? 4 : 8;
+constexpr int kNodeBytes = 16 * kNodeFloat4;
+static_assert(kNodeWidth == 2 || kNodeWidth == 4, "BVH width must be 2 or 4");
 constexpr int kLeafMaxTris = 4;
-constexpr int kNodeFloat4 = 4;
 constexpr int kTriFloat4 = 3;
 constexpr int kMatFloat4 = 3;    // (kd, n), (ks, 0), (kr, 0)
 constexpr int kLightFloat4 = 2;  // (pos, 0), (I, 0)
 constexpr float kSecondaryTmin = 1e-4f;
-constexpr int kStackMax = 128;   // bound on traversal stack depth (BVH depth <= 97 for 63-bit keys)
+constexpr int kStackMax = 128;   // traversal stack entries per lane (LDS ring + spill area)
 
 struct DevScene {
   const float4* nodes;
@@ -88,7 +98,7 @@ struct BuildPlan {
   size_t storage_bytes;
   // scratch
   size_t keys0_off, keys1_off, ids0_off, ids1_off, lo_off, hi_off, partial_off, hist_off, children_off,
-      parent_off, flags_off, nodebox_off, status_off, range_off;
+      parent_off, flags_off, nodebox_off, status_off, range_off, frontier_off[2], sel_off, nint_off;
   size_t scratch_bytes;
   int64_t num_blocks_prep, num_sort_blocks;
   bool bvh;
