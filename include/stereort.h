@@ -190,7 +190,10 @@ typedef struct {
 enum {
   RT_FLAG_PATH_IDS = 1u << 0,   /* write path_prims / shadow_state */
   RT_FLAG_COUNT_WORK = 1u << 1, /* count node visits and triangle tests (slower kernels) */
-  RT_FLAG_BRUTE_FORCE = 1u << 2 /* test every triangle even if the scene has a BVH */
+  RT_FLAG_BRUTE_FORCE = 1u << 2, /* test every triangle even if the scene has a BVH */
+  RT_FLAG_READBACK_MEMCPY = 1u << 3 /* read back with hipMemcpyAsync.  By default a narrow copy kernel
+                                       writes through the pinned buffer's device view (hipMemcpyAsync is
+                                       used when host_radiance has none) */
 };
 
 /* Device workspace bytes for rendering a whole stereo frame of `camera` with
@@ -205,7 +208,8 @@ typedef struct rt_timer_s* rt_timer;
 
 /* Renders both eyes of `camera` into `out`.  Asynchronous on `stream`.  If
  * out->host_radiance is set, the radiance is also copied into that pinned
- * host memory on `copy_stream` (NULL: on `stream`) once rendering is done;
+ * host memory (hipHostMalloc) on `copy_stream` (NULL: on `stream`) once
+ * rendering is done;
  * synchronise copy_stream before reading it.  `timer` (optional) records
  * per-kernel device time (see rt_timer_read).  The workspace must be 256-byte
  * aligned and must not be used by another render in flight. */

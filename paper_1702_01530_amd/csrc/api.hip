@@ -209,7 +209,8 @@ rt_status check_output(const rt_stereo_output* o, uint32_t flags) {
   return RT_OK;
 }
 
-constexpr uint32_t kKnownFlags = RT_FLAG_PATH_IDS | RT_FLAG_COUNT_WORK | RT_FLAG_BRUTE_FORCE;
+constexpr uint32_t kKnownFlags = RT_FLAG_PATH_IDS | RT_FLAG_COUNT_WORK | RT_FLAG_BRUTE_FORCE | RT_FLAG_READBACK_MEMCPY;
+constexpr int kReadbackBlocks = 32;
 
 rt_status render_one(const rt_scene_s* scene, const rt_stereo_camera* cam, const rt_stereo_output* out, char* ws,
                      size_t ws_bytes, uint32_t flags, hipStream_t stream, hipStream_t copy_stream,
@@ -253,9 +254,21 @@ rt_status render_one(const rt_scene_s* scene, const rt_stereo_camera* cam, const
       (void)hipEventDestroy(ev);
       if (e != hipSuccess) return hip_fail(e, "stream ordering for readback");
     }
+    // Default: a narrow copy kernel writes through the pinned buffer's device view, so the copy
+    // does not crowd the next frame's traversal off the compute units (hipMemcpyAsync's blit
+    // kernel does).  hipMemcpyAsync is used with RT_FLAG_READBACK_MEMCPY or when the buffer has
+    // no device view (not pinned and mapped).
+    void* dview[2] = {nullptr, nullptr};
+    bool use_kernel = (flags & RT_FLAG_READBACK_MEMCPY) == 0;
+    for (int eye = 0; eye < 2 && use_kernel; ++eye)
+      if (hipHostGetDevicePointer(&dview[eye], out->host_radiance[eye], 0) != hipSuccess || !dview[eye]) {
+        (void)hipGetLastError();
+        use_kernel = false;
+      }
     if (timer) srt::timer_begin(timer, RT_STAGE_READBACK, cs);
     for (int eye = 0; eye < 2 && e == hipSuccess; ++eye)
-      e = hipMemcpyAsync(out->host_radiance[eye], out->radiance[eye], bytes, hipMemcpyDeviceToHost, cs);
+      e = use_kernel ? srt::copy_to_host(out->radiance[eye], dview[eye], bytes, kReadbackBlocks, cs)
+                     : hipMemcpyAsync(out->host_radiance[eye], out->radiance[eye], bytes, hipMemcpyDeviceToHost, cs);
     if (timer) srt::timer_end(timer, RT_STAGE_READBACK, cs);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (readback)");
   }

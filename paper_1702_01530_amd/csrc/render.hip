@@ -394,6 +394,8 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
     for (int l = 0; l < L; ++l) total += round64(a.ctr->shadow_count[depth - 1][l]);
   uint32_t c_nodes = 0, c_tris = 0, s_nodes = 0, s_tris = 0;
   while (true) {
+    // one wave-wide batch of 64 work items per atomic (larger grabs unbalance the launch's end, and
+    // refilling single lanes stalls the wave on every refill)
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(&a.ctr->trace_work[depth], 64u);
     base = __shfl(base, 0);
@@ -690,6 +692,22 @@ __global__ void k_finish(const Counters* ctr, int D, int L, int64_t* out) {
   out[RT_COUNT_ERRORS] += ctr->error;
 }
 
+// Readback: a grid of a few workgroups streams the radiance into mapped pinned host memory, so the
+// copy leaves the compute units to the next frame's traversal.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kBlock) void k_copy_to_host16(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                           size_t n) {
+  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock)
+    __builtin_nontemporal_store(src[i], &dst[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_to_host4(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                                                          size_t n) {
+  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += size_t(gridDim.x) * kBlock)
+    __builtin_nontemporal_store(src[i], &dst[i]);
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <typename K>
@@ -702,6 +720,18 @@ hipError_t launch(K kernel, unsigned grid, const KArgs& a, int depth, hipStream_
 }
 
 }  // namespace
+
+hipError_t copy_to_host(const void* src, void* host_dst_device_view, size_t bytes, int blocks, hipStream_t s) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(host_dst_device_view);
+  if (((a | b) & 15u) == 0 && bytes % 16 == 0) {
+    k_copy_to_host16<<<blocks, kBlock, 0, s>>>(static_cast<const u32x4*>(src),
+                                               static_cast<u32x4*>(host_dst_device_view), bytes / 16);
+  } else {
+    k_copy_to_host4<<<blocks, kBlock, 0, s>>>(static_cast<const uint32_t*>(src),
+                                              static_cast<uint32_t*>(host_dst_device_view), bytes / 4);
+  }
+  return hipGetLastError();
+}
 
 int trace_grid_size(int device) {
   static int cached[64] = {0};

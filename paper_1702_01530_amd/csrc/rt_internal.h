@@ -146,6 +146,8 @@ struct RenderArgs {
 };
 
 hipError_t render_chunk(const RenderArgs& a, hipStream_t stream, TimerImpl* timer);
+// Copies `bytes` (a multiple of 4) from device memory into pinned host memory through its device view.
+hipError_t copy_to_host(const void* src, void* host_dst_device_view, size_t bytes, int blocks, hipStream_t s);
 hipError_t add_ray_counts(const RenderArgs& a, hipStream_t stream);
 
 }  // namespace srt

@@ -133,10 +133,10 @@ def output_struct(o: dict) -> rt.rt_stereo_output:
 
 def render_stereo(gs: GpuScene, cam, *, path_ids=False, count_work=False, brute_force=False, host=False,
                   workspace: Workspace | None = None, outputs: dict | None = None, stream=None, copy_stream=None,
-                  timer=None) -> dict:
+                  timer=None, readback_memcpy=False) -> dict:
     """Renders both eyes; returns the output tensors (valid after the stream is synchronised)."""
     flags = (rt.RT_FLAG_PATH_IDS if path_ids else 0) | (rt.RT_FLAG_COUNT_WORK if count_work else 0) | (
-        rt.RT_FLAG_BRUTE_FORCE if brute_force else 0)
+        rt.RT_FLAG_BRUTE_FORCE if brute_force else 0) | (rt.RT_FLAG_READBACK_MEMCPY if readback_memcpy else 0)
     camst = rt.make_camera_struct(cam)
     if workspace is None:
         workspace = Workspace(rt.rt_render_workspace_size(camst, gs.num_lights), gs.device)

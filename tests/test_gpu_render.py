@@ -175,6 +175,22 @@ def test_pinned_readback_and_timer(torch_cuda):
     gs.close()
 
 
+@pytest.mark.parametrize("size", [(256, 256), (37, 23)])  # the second eye of 37x23 is not 16-byte aligned
+@pytest.mark.parametrize("memcpy", [False, True])
+def test_readback_matches_device(torch_cuda, size, memcpy):
+    torch = torch_cuda
+    from paper_1702_01530_amd.stereo import GpuScene, render_stereo
+    scene, cam = sg.make_spheres_scene()
+    cam = cam.resized(*size)
+    gs = GpuScene(scene)
+    copy = torch.cuda.Stream()
+    out = render_stereo(gs, cam, host=True, copy_stream=copy, readback_memcpy=memcpy)
+    copy.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(out["host_radiance"], out["radiance"].cpu())
+    gs.close()
+
+
 def test_invalid_arguments_gpu(torch_cuda):
     torch = torch_cuda
     from paper_1702_01530_amd import rt
