@@ -83,6 +83,68 @@ def cpu_baseline(scene, cam, target_s: float = 15.0) -> dict:
             "seconds": dt, "paths": n}
 
 
+def bench_batch(args):
+    """Batched mode: 64 stereo pairs of mixed resolution over 8 resident scenes (1k-500k triangles),
+    rendered as one batch (rt_render_batch) versus one rt_render_stereo launch sequence per pair."""
+    import numpy as np
+    import torch
+    import scenegen as sg
+    from paper_1702_01530_amd import rt
+    from paper_1702_01530_amd.stereo import GpuScene, Workspace, alloc_outputs, render_batch, render_stereo
+    dev = torch.device("cuda:0")
+    scenes, spec = sg.make_batch_workload()
+    gss = [GpuScene(s) for s in scenes]
+    pairs = [(gss[k], cam) for k, cam in spec]
+    paths = sum(2 * c.width * c.height for _, c in pairs)
+    log(f"[batch] {len(pairs)} stereo pairs, {len(scenes)} scenes ({min(s.num_triangles for s in scenes)}-"
+        f"{max(s.num_triangles for s in scenes)} triangles), {paths / 1e6:.1f}M paths")
+    outs = [alloc_outputs(cam, gs.num_lights, dev, counts=(i == 0)) for i, (gs, cam) in enumerate(pairs)]
+    ws_single = Workspace(max(rt.rt_render_workspace_size(rt.make_camera_struct(c), g.num_lights) for g, c in pairs))
+    items = (rt.rt_batch_item * len(pairs))()
+    for i, (g, c) in enumerate(pairs):
+        items[i].scene, items[i].camera = g.handle, rt.make_camera_struct(c)
+    ws_batch = Workspace(rt.rt_render_batch_workspace_size(items))
+    log(f"[batch] workspaces: per-frame {ws_single.nbytes / 1e9:.2f} GB, batch {ws_batch.nbytes / 1e9:.2f} GB")
+    outs[0]["ray_counts"].zero_()
+    render_batch(pairs, outputs=outs, workspace=ws_batch)
+    torch.cuda.synchronize()
+    rays = int(outs[0]["ray_counts"][:3].sum())
+
+    def per_frame():
+        for (g, c), o in zip(pairs, outs):
+            render_stereo(g, c, workspace=ws_single, outputs=o)
+
+    def batched():
+        render_batch(pairs, outputs=outs, workspace=ws_batch)
+
+    res = {}
+    for name, fn in (("per_frame", per_frame), ("batched", batched)):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(args.steps):
+            fn()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / args.steps
+        res[name] = {"ms_per_batch": ms, "stereo_fps": len(pairs) / (ms * 1e-3), "mrays_s": rays / (ms * 1e-3) / 1e6}
+        log(f"[batch] {name}: {ms:.2f} ms per 64 pairs = {res[name]['stereo_fps']:.1f} stereo frames/s, "
+            f"{res[name]['mrays_s']:.0f} Mrays/s")
+    out = {"metric": "stereo frames/s, batched vs per-frame (64 mixed pairs, 8 resident scenes)",
+           "value": res["batched"]["stereo_fps"], "unit": "stereo frames/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res["batched"]["ms_per_batch"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batch64", "pairs": len(pairs), "scenes": len(scenes), "paths": paths,
+                      "rays_per_batch": rays},
+           "batched": res["batched"], "per_frame": res["per_frame"],
+           "speedup": res["per_frame"]["ms_per_batch"] / res["batched"]["ms_per_batch"]}
+    for g in gss:
+        g.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +183,8 @@ def main():
         return
 
     rt.lib()
+    if args.workload == "batch64":
+        return bench_batch(args)
     scene, cam = workload(args.workload)
     log(f"[bench] workload {args.workload}: {scene.num_triangles} triangles, {cam.width}x{cam.height} per eye, "
         f"depth {cam.max_depth}, {scene.num_lights} lights")

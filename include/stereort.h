@@ -223,9 +223,15 @@ typedef struct {
   rt_stereo_output out;
 } rt_batch_item;
 
-/* Renders n stereo pairs (any mix of scenes and resolutions) on `stream`
- * sharing one workspace sized by rt_render_batch_workspace_size.  Each
- * item's output is identical to rendering it alone with rt_render_stereo. */
+/* Renders n >= 1 stereo pairs (any mix of scenes, resolutions, depths and
+ * baselines) on `stream` as one pipeline: the paths of all items share the
+ * ray queues and every traversal launch, so small renders fill the GPU
+ * together instead of one after another.  Each item's outputs are bitwise
+ * identical to rendering it alone with rt_render_stereo.  The workspace
+ * (rt_render_batch_workspace_size for one pass; less makes more passes)
+ * starts with the batch's item table.  Host readbacks are ordered on `stream`.
+ * The batch's total ray counts are added to items[0].out.ray_counts if set;
+ * other items' ray_counts are not written. */
 rt_status rt_render_batch_workspace_size(const rt_batch_item* items, int32_t n, size_t* bytes);
 rt_status rt_render_batch(const rt_batch_item* items, int32_t n, void* workspace, size_t workspace_bytes,
                           uint32_t flags, void* stream, rt_timer timer);

@@ -212,6 +212,61 @@ rt_status check_output(const rt_stereo_output* o, uint32_t flags) {
 constexpr uint32_t kKnownFlags = RT_FLAG_PATH_IDS | RT_FLAG_COUNT_WORK | RT_FLAG_BRUTE_FORCE | RT_FLAG_READBACK_MEMCPY;
 constexpr int kReadbackBlocks = 32;
 
+srt::DevOutputs dev_outputs(const rt_stereo_output* o, uint32_t flags) {
+  srt::DevOutputs d{};
+  const bool ids = (flags & RT_FLAG_PATH_IDS) != 0;
+  for (int e = 0; e < 2; ++e) {
+    d.radiance[e] = o->radiance[e];
+    d.hit_t[e] = o->hit_t[e];
+    d.hit_prim[e] = o->hit_prim[e];
+    d.path_prims[e] = ids ? o->path_prims[e] : nullptr;
+    d.shadow_state[e] = ids ? o->shadow_state[e] : nullptr;
+  }
+  return d;
+}
+
+// Copies both eyes' radiance into the pinned host buffers of `out`, ordered after `stream`.
+rt_status readback(const rt_stereo_camera* cam, const rt_stereo_output* out, uint32_t flags, hipStream_t stream,
+                   hipStream_t copy_stream, srt::TimerImpl* timer) {
+  if (!out->host_radiance[0]) return RT_OK;
+  const size_t bytes = size_t(cam->width) * size_t(cam->height) * 12;
+  hipStream_t cs = copy_stream ? copy_stream : stream;
+  hipError_t e = hipSuccess;
+  if (cs != stream) {
+    hipEvent_t ev;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    e = hipEventRecord(ev, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return hip_fail(e, "stream ordering for readback");
+  }
+  // Default: a narrow copy kernel writes through the pinned buffer's device view, so the copy
+  // does not crowd the next frame's traversal off the compute units (hipMemcpyAsync's blit
+  // kernel does).  hipMemcpyAsync is used with RT_FLAG_READBACK_MEMCPY or when the buffer has
+  // no device view (not pinned and mapped).
+  void* dview[2] = {nullptr, nullptr};
+  bool use_kernel = (flags & RT_FLAG_READBACK_MEMCPY) == 0;
+  for (int eye = 0; eye < 2 && use_kernel; ++eye)
+    if (hipHostGetDevicePointer(&dview[eye], out->host_radiance[eye], 0) != hipSuccess || !dview[eye]) {
+      (void)hipGetLastError();
+      use_kernel = false;
+    }
+  if (timer) srt::timer_begin(timer, RT_STAGE_READBACK, cs);
+  for (int eye = 0; eye < 2 && e == hipSuccess; ++eye)
+    e = use_kernel ? srt::copy_to_host(out->radiance[eye], dview[eye], bytes, kReadbackBlocks, cs)
+                   : hipMemcpyAsync(out->host_radiance[eye], out->radiance[eye], bytes, hipMemcpyDeviceToHost, cs);
+  if (timer) srt::timer_end(timer, RT_STAGE_READBACK, cs);
+  if (e != hipSuccess) return hip_fail(e, "readback");
+  return RT_OK;
+}
+
+rt_status current_device(int* dev) {
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  return RT_OK;
+}
+
 rt_status render_one(const rt_scene_s* scene, const rt_stereo_camera* cam, const rt_stereo_output* out, char* ws,
                      size_t ws_bytes, uint32_t flags, hipStream_t stream, hipStream_t copy_stream,
                      srt::TimerImpl* timer) {
@@ -224,56 +279,34 @@ rt_status render_one(const rt_scene_s* scene, const rt_stereo_camera* cam, const
     return fail(RT_ERR_BUFFER_TOO_SMALL, "workspace of %zu bytes is below the minimum of %zu bytes", ws_bytes, need);
   }
   int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  rt_status st = current_device(&dev);
+  if (st != RT_OK) return st;
   if (dev != scene->device)
     return fail(RT_ERR_INVALID_ARGUMENT, "scene was built on device %d, current device is %d", scene->device, dev);
   plan.grid_trace = srt::trace_grid_size(dev);
-  srt::RenderArgs ra;
-  ra.scene = scene->dev;
-  ra.cam = make_dev_camera(cam);
-  ra.out = out;
+  srt::RenderArgs ra{};
+  ra.one.sc = scene->dev;
+  ra.one.cam = make_dev_camera(cam);
+  ra.one.out = dev_outputs(out, flags);
+  ra.one.path_offset = 0;
+  ra.items = nullptr;
+  ra.num_items = 1;
+  ra.max_lights = scene->dev.L;
+  ra.max_depth = cam->max_depth;
+  ra.ray_counts = out->ray_counts;
   ra.flags = flags;
   ra.ws = ws;
   ra.plan = plan;
   for (int64_t begin = 0; begin < total; begin += chunk) {
     ra.path_begin = begin;
     ra.path_count = std::min(chunk, total - begin);
-    e = srt::render_chunk(ra, stream, timer);
+    hipError_t e = srt::render_chunk(ra, stream, timer);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
-  if (out->host_radiance[0]) {
-    const size_t bytes = size_t(cam->width) * size_t(cam->height) * 12;
-    hipStream_t cs = copy_stream ? copy_stream : stream;
-    if (cs != stream) {
-      hipEvent_t ev;
-      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-      e = hipEventRecord(ev, stream);
-      if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
-      (void)hipEventDestroy(ev);
-      if (e != hipSuccess) return hip_fail(e, "stream ordering for readback");
-    }
-    // Default: a narrow copy kernel writes through the pinned buffer's device view, so the copy
-    // does not crowd the next frame's traversal off the compute units (hipMemcpyAsync's blit
-    // kernel does).  hipMemcpyAsync is used with RT_FLAG_READBACK_MEMCPY or when the buffer has
-    // no device view (not pinned and mapped).
-    void* dview[2] = {nullptr, nullptr};
-    bool use_kernel = (flags & RT_FLAG_READBACK_MEMCPY) == 0;
-    for (int eye = 0; eye < 2 && use_kernel; ++eye)
-      if (hipHostGetDevicePointer(&dview[eye], out->host_radiance[eye], 0) != hipSuccess || !dview[eye]) {
-        (void)hipGetLastError();
-        use_kernel = false;
-      }
-    if (timer) srt::timer_begin(timer, RT_STAGE_READBACK, cs);
-    for (int eye = 0; eye < 2 && e == hipSuccess; ++eye)
-      e = use_kernel ? srt::copy_to_host(out->radiance[eye], dview[eye], bytes, kReadbackBlocks, cs)
-                     : hipMemcpyAsync(out->host_radiance[eye], out->radiance[eye], bytes, hipMemcpyDeviceToHost, cs);
-    if (timer) srt::timer_end(timer, RT_STAGE_READBACK, cs);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (readback)");
-  }
-  return RT_OK;
+  return readback(cam, out, flags, stream, copy_stream, timer);
 }
+
+size_t batch_table_bytes(int32_t n) { return (size_t(n) * sizeof(srt::DevItem) + 255) & ~size_t(255); }
 
 }  // namespace
 
@@ -432,36 +465,80 @@ rt_status rt_render_stereo(rt_scene scene, const rt_stereo_camera* camera, const
 }
 
 rt_status rt_render_batch_workspace_size(const rt_batch_item* items, int32_t n, size_t* bytes) {
-  if (n < 0 || (n > 0 && !items) || !bytes) return fail(RT_ERR_INVALID_ARGUMENT, "bad batch arguments");
-  size_t best = 0;
-  for (int i = 0; i < n; ++i) {
-    if (!items[i].scene) return fail(RT_ERR_INVALID_ARGUMENT, "item %d has no scene", i);
-    size_t b = 0;
-    rt_status s = rt_render_workspace_size(&items[i].camera, items[i].scene->dev.L, &b);
-    if (s != RT_OK) return s;
-    best = std::max(best, b);
-  }
-  *bytes = best;
-  return ok();
-}
-
-rt_status rt_render_batch(const rt_batch_item* items, int32_t n, void* workspace, size_t workspace_bytes,
-                          uint32_t flags, void* stream, rt_timer timer) {
-  if (n < 0 || (n > 0 && !items)) return fail(RT_ERR_INVALID_ARGUMENT, "bad batch arguments");
-  if (flags & ~kKnownFlags) return fail(RT_ERR_INVALID_ARGUMENT, "unknown render flags 0x%x", flags);
-  if (!workspace || !aligned256(workspace))
-    return fail(RT_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");
+  if (n < 1 || !items || !bytes) return fail(RT_ERR_INVALID_ARGUMENT, "bad batch arguments");
+  int64_t total = 0;
+  int32_t lmax = 0;
   for (int i = 0; i < n; ++i) {
     if (!items[i].scene) return fail(RT_ERR_INVALID_ARGUMENT, "item %d has no scene", i);
     rt_status s = validate_camera(&items[i].camera);
     if (s != RT_OK) return s;
-    if ((s = check_output(&items[i].out, flags)) != RT_OK) return s;
+    total += total_paths(&items[i].camera);
+    lmax = std::max(lmax, items[i].scene->dev.L);
   }
+  srt::RenderPlan plan;
+  *bytes = batch_table_bytes(n) + srt::plan_render(std::min(total, kMaxChunk), lmax, 0, &plan);
+  return ok();
+}
+
+rt_status rt_render_batch(const rt_batch_item* items, int32_t n, void* workspace, size_t workspace_bytes,
+                          uint32_t flags, void* stream_in, rt_timer timer) {
+  if (n < 1 || !items) return fail(RT_ERR_INVALID_ARGUMENT, "bad batch arguments");
+  if (flags & ~kKnownFlags) return fail(RT_ERR_INVALID_ARGUMENT, "unknown render flags 0x%x", flags);
+  if (!workspace || !aligned256(workspace))
+    return fail(RT_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");
+  int dev = 0;
+  rt_status st = current_device(&dev);
+  if (st != RT_OK) return st;
+  std::vector<srt::DevItem> table(static_cast<size_t>(n));
+  int64_t total = 0;
+  int32_t lmax = 0, dmax = 0;
   for (int i = 0; i < n; ++i) {
-    rt_status s = render_one(items[i].scene, &items[i].camera, &items[i].out, static_cast<char*>(workspace),
-                             workspace_bytes, flags, static_cast<hipStream_t>(stream), nullptr, timer);
-    if (s != RT_OK) return s;
+    const rt_batch_item& it = items[i];
+    if (!it.scene) return fail(RT_ERR_INVALID_ARGUMENT, "item %d has no scene", i);
+    if (it.scene->device != dev)
+      return fail(RT_ERR_INVALID_ARGUMENT, "item %d's scene was built on device %d, current device is %d", i,
+                  it.scene->device, dev);
+    if ((st = validate_camera(&it.camera)) != RT_OK) return st;
+    if ((st = check_output(&it.out, flags)) != RT_OK) return st;
+    srt::DevItem& d = table[size_t(i)];
+    d.sc = it.scene->dev;
+    d.cam = make_dev_camera(&it.camera);
+    d.out = dev_outputs(&it.out, flags);
+    d.path_offset = total;
+    total += total_paths(&it.camera);
+    lmax = std::max(lmax, it.scene->dev.L);
+    dmax = std::max(dmax, it.camera.max_depth);
   }
+  if (total >= (int64_t(1) << 31)) return fail(RT_ERR_UNSUPPORTED, "a batch is limited to 2^31 paths");
+  const size_t tbytes = batch_table_bytes(n);
+  if (workspace_bytes <= tbytes) return fail(RT_ERR_BUFFER_TOO_SMALL, "workspace smaller than the item table");
+  srt::RenderPlan plan;
+  const int64_t chunk = chunk_for(total, lmax, workspace_bytes - tbytes, &plan);
+  if (chunk == 0) return fail(RT_ERR_BUFFER_TOO_SMALL, "workspace of %zu bytes is too small", workspace_bytes);
+  plan.grid_trace = srt::trace_grid_size(dev);
+  hipStream_t stream = static_cast<hipStream_t>(stream_in);
+  char* ws = static_cast<char*>(workspace);
+  srt::DevItem* dtable = reinterpret_cast<srt::DevItem*>(ws);
+  hipError_t e = srt::upload_items(table.data(), n, dtable, stream);
+  if (e != hipSuccess) return hip_fail(e, "item table upload");
+  srt::RenderArgs ra{};
+  ra.items = dtable;
+  ra.num_items = n;
+  ra.max_lights = lmax;
+  ra.max_depth = dmax;
+  ra.ray_counts = items[0].out.ray_counts;
+  ra.flags = flags;
+  ra.ws = ws + tbytes;
+  ra.plan = plan;
+  for (int64_t begin = 0; begin < total; begin += chunk) {
+    ra.path_begin = begin;
+    ra.path_count = std::min(chunk, total - begin);
+    e = srt::render_chunk(ra, stream, timer);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  for (int i = 0; i < n; ++i)
+    if ((st = readback(&items[i].camera, &items[i].out, flags, stream, nullptr, timer)) != RT_OK) return st;
+  if (timer && timer->error != hipSuccess) return hip_fail(timer->error, "timer event");
   return ok();
 }
 

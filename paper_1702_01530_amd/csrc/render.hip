@@ -82,29 +82,47 @@ __device__ inline uint32_t round64(uint32_t x) { return (x + 63u) & ~63u; }
 // ---------------------------------------------------------------------------------------------
 
 struct KArgs {
-  DevScene sc;
-  DevCamera cam;
+  DevItem one;            // single render (MULTI = false)
+  const DevItem* items;   // batch table (MULTI = true)
+  int32_t num_items;
+  int32_t lstride;        // light slots per entry in contrib/vis (max lights over the items)
+  int32_t dmax;           // max reflection depth over the items
   Counters* ctr;
-  float4* ro[2];       // mirror/primary ray queue by depth parity: origin + path id bits
+  float4* ro[2];       // mirror/primary ray queue by depth parity: origin + pass-local path index bits
   float4* rd[2];       // direction + excluded primitive key bits
   float4* thr[2];      // throughput
   float2* hit;         // (t, key bits) of the closest-hit rays of the current depth
-  uint2* resinfo[2];   // per entry of a depth: (path id, mask of lights with a shadow ray)
-  float4* srec[2];     // shadow records [L][cap]: (origin, excluded key bits)
-  uint32_t* sowner[2]; // [L][cap]: entry that owns the record
-  float4* contrib[2];  // [cap][L]: the light's term times throughput
-  uint8_t* vis[2];     // [cap][L]: 1 = light visible
+  uint2* resinfo[2];   // per entry of a depth: (pass-local path index, mask of lights with a shadow ray)
+  float4* srec[2];     // shadow records [light][cap]: (origin, excluded key bits)
+  uint32_t* sowner[2]; // [light][cap]: entry that owns the record
+  float4* contrib[2];  // [cap][lstride]: the light's term times throughput
+  uint8_t* vis[2];     // [cap][lstride]: 1 = light visible
   uint32_t* gstack;
-  float* radiance[2];
-  float* hit_t[2];
-  int32_t* hit_prim[2];
-  int32_t* path_prims[2];
-  uint8_t* shadow_state[2];
   int64_t path_begin, path_count;
   uint32_t cap;           // entries per queue
   int32_t brute;
   int32_t trace_threads;  // threads in the persistent traversal grid (gstack stride)
 };
+
+// The item a path belongs to: binary search over the items' first path ids.
+template <bool MULTI>
+__device__ inline int item_of(const KArgs& a, int64_t p) {
+  if (!MULTI) return 0;
+  int lo = 0, hi = a.num_items - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.items[mid].path_offset <= p)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <bool MULTI>
+__device__ inline const DevItem& item_ref(const KArgs& a, int k) {
+  return MULTI ? a.items[k] : a.one;
+}
 
 // ---------------------------------------------------------------------------------------------
 // Camera
@@ -376,22 +394,22 @@ __device__ inline void add_work(Counters* ctr, int slot, uint32_t v) {
 #define SRT_TRACE_ATTR
 #endif
 
-template <bool COUNT>
+template <bool COUNT, bool MULTI>
 __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int depth) {
   __shared__ uint32_t lstack[kStackLds * kBlock];
   const int lane = lane_id();
   const int gtid = blockIdx.x * kBlock + threadIdx.x;
   Stack st{&lstack[threadIdx.x], a.gstack + gtid, a.trace_threads, 0, false};
-  const int L = a.sc.L;
-  const bool closest = depth <= a.cam.D;
+  const int LS = a.lstride;
+  const bool closest = depth <= a.dmax;
   const bool shadows = depth >= 1;
   const int q = depth & 1;
-  const int sp = (depth + 1) & 1;  // parity of depth - 1
+  const int sq = (depth + 1) & 1;  // parity of depth - 1
   const uint32_t nc = closest ? (depth == 0 ? uint32_t(a.path_count) : a.ctr->refl_count[depth]) : 0u;
   const uint32_t nc_pad = round64(nc);
   uint32_t total = nc_pad;
   if (shadows)
-    for (int l = 0; l < L; ++l) total += round64(a.ctr->shadow_count[depth - 1][l]);
+    for (int l = 0; l < LS; ++l) total += round64(a.ctr->shadow_count[depth - 1][l]);
   uint32_t c_nodes = 0, c_tris = 0, s_nodes = 0, s_tris = 0;
   while (true) {
     // one wave-wide batch of 64 work items per atomic (larger grabs unbalance the launch's end, and
@@ -407,13 +425,16 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
         float3 o, d;
         int exclude = -1;
         bool valid = true;
+        int k;
         if (depth == 0) {
-          int eye, x, y;
           const int64_t p = a.path_begin + e;
-          valid = path_pixel(a.cam, p, &eye, &x, &y);
+          k = item_of<MULTI>(a, p);
+          const DevItem& it = item_ref<MULTI>(a, k);
+          int eye, x, y;
+          valid = path_pixel(it.cam, p - it.path_offset, &eye, &x, &y);
           if (valid) {
-            primary_ray(a.cam, eye, x, y, &o, &d);
-            a.ro[q][e] = make_float4(o.x, o.y, o.z, __int_as_float(int(p)));
+            primary_ray(it.cam, eye, x, y, &o, &d);
+            a.ro[q][e] = make_float4(o.x, o.y, o.z, __int_as_float(int(e)));
             a.rd[q][e] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
           } else {
             a.ro[q][e] = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
@@ -423,10 +444,12 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
           o = f3(ro);
           d = f3(rd);
           exclude = __float_as_int(rd.w);
+          k = item_of<MULTI>(a, a.path_begin + uint32_t(__float_as_int(ro.w)));
         }
         if (valid) {
+          const DevScene sc = item_ref<MULTI>(a, k).sc;
           Best b{INFINITY, -1, 0x7fffffff};
-          traverse<false, COUNT>(a.sc, o, d, depth == 0 ? 0.0f : kSecondaryTmin, exclude, a.brute != 0, b, st,
+          traverse<false, COUNT>(sc, o, d, depth == 0 ? 0.0f : kSecondaryTmin, exclude, a.brute != 0, b, st,
                                  c_nodes, c_tris);
           a.hit[e] = make_float2(b.t, __int_as_float(b.key));
         }
@@ -436,7 +459,7 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
       uint32_t start = nc_pad;
       int l = 0;
       uint32_t cnt = a.ctr->shadow_count[depth - 1][0];
-      while (l + 1 < L && base >= start + round64(cnt)) {
+      while (l + 1 < LS && base >= start + round64(cnt)) {
         start += round64(cnt);
         ++l;
         cnt = a.ctr->shadow_count[depth - 1][l];
@@ -444,16 +467,18 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
       const uint32_t i = base - start + lane;
       if (i < cnt) {
         const size_t slot = size_t(l) * a.cap + i;
-        const float4 rec = a.srec[sp][slot];
-        const uint32_t owner = a.sowner[sp][slot];
+        const float4 rec = a.srec[sq][slot];
+        const uint32_t owner = a.sowner[sq][slot];
+        const int k = MULTI ? item_of<MULTI>(a, a.path_begin + a.resinfo[sq][owner].x) : 0;
+        const DevScene sc = item_ref<MULTI>(a, k).sc;
         const float3 P = f3(rec);
-        const float3 Lv = f3(a.sc.lights[2 * l]) - P;
+        const float3 Lv = f3(sc.lights[2 * l]) - P;
         const float dist = sqrtf(dot(Lv, Lv));
         const float3 Ld = (1.0f / dist) * Lv;
         Best b{dist, -1, 0};
-        traverse<true, COUNT>(a.sc, P, Ld, kSecondaryTmin, __float_as_int(rec.w), a.brute != 0, b, st, s_nodes,
+        traverse<true, COUNT>(sc, P, Ld, kSecondaryTmin, __float_as_int(rec.w), a.brute != 0, b, st, s_nodes,
                               s_tris);
-        a.vis[sp][size_t(owner) * L + l] = b.key < 0 ? 1 : 0;
+        a.vis[sq][size_t(owner) * LS + l] = b.key < 0 ? 1 : 0;
       }
     }
   }
@@ -505,16 +530,14 @@ __device__ inline int32_t out_id(const DevScene& sc, int key) {
 // ballots, a block prefix over the waves and one atomic per block and queue.
 // ---------------------------------------------------------------------------------------------
 
-template <bool PATH_IDS>
+template <bool PATH_IDS, bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_shade(KArgs a, int depth) {
   __shared__ uint32_t wcnt[kWaves][RT_MAX_LIGHTS + 1];
   __shared__ uint32_t bbase[RT_MAX_LIGHTS + 1];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int q = depth & 1, nq = (depth + 1) & 1;
   const uint32_t total = depth == 0 ? uint32_t(a.path_count) : a.ctr->refl_count[depth];
-  const int L = a.sc.L;
-  const bool may_reflect = depth < a.cam.D;
-  const int D1 = a.cam.D + 1;
+  const int LS = a.lstride;
   uint32_t n_primary = 0;
   for (uint32_t base = blockIdx.x * kBlock; base < total; base += gridDim.x * kBlock) {  // block-uniform loop
     const uint32_t e = base + threadIdx.x;
@@ -537,42 +560,49 @@ __global__ __launch_bounds__(kBlock) void k_shade(KArgs a, int depth) {
     bool spawn = false;
     float3 P = make_float3(0.f, 0.f, 0.f), N = P, V = P, rdir = P, kr3 = P;
     float4 m0 = make_float4(0.f, 0.f, 0.f, 0.f), m1 = m0;
+    const float4* lights = nullptr;
     const int key = __float_as_int(hit.y);
     if (active) {
+      const uint32_t lp = uint32_t(__float_as_int(ro.w));
+      const int64_t p = a.path_begin + lp;
+      const DevItem& it = item_ref<MULTI>(a, item_of<MULTI>(a, p));
+      const DevScene& sc = it.sc;
+      const int L = sc.L, D1 = it.cam.D + 1;
+      lights = sc.lights;
       int eye, x, y;
-      path_pixel(a.cam, int64_t(__float_as_int(ro.w)), &eye, &x, &y);
-      const int64_t pix = int64_t(y) * a.cam.W + x;
-      float* rad = a.radiance[eye] + 3 * pix;
+      path_pixel(it.cam, p - it.path_offset, &eye, &x, &y);
+      const int64_t pix = int64_t(y) * it.cam.W + x;
+      float* rad = it.out.radiance[eye] + 3 * pix;
       const float3 o = f3(ro), d = f3(rd);
       if (depth == 0) {
         ++n_primary;
-        if (a.hit_t[eye]) a.hit_t[eye][pix] = hit.x;
-        if (a.hit_prim[eye]) a.hit_prim[eye][pix] = out_id(a.sc, key);
+        if (it.out.hit_t[eye]) it.out.hit_t[eye][pix] = hit.x;
+        if (it.out.hit_prim[eye]) it.out.hit_prim[eye][pix] = out_id(sc, key);
         if (PATH_IDS) {
-          for (int k = 0; k < D1; ++k) a.path_prims[eye][pix * D1 + k] = -2;
-          for (int k = 0; k < D1 * L; ++k) a.shadow_state[eye][pix * D1 * L + k] = 0;
+          for (int k = 0; k < D1; ++k) it.out.path_prims[eye][pix * D1 + k] = -2;
+          for (int k = 0; k < D1 * L; ++k) it.out.shadow_state[eye][pix * D1 * L + k] = 0;
         }
       }
-      if (PATH_IDS) a.path_prims[eye][pix * D1 + depth] = out_id(a.sc, key);
+      if (PATH_IDS) it.out.path_prims[eye][pix * D1 + depth] = out_id(sc, key);
       float3 add;
       if (key < 0) {
-        add = mul(thr, make_float3(a.sc.background[0], a.sc.background[1], a.sc.background[2]));
+        add = mul(thr, make_float3(sc.background[0], sc.background[1], sc.background[2]));
       } else {
         P = o + hit.x * d;
-        const float3 Ng = geometric_normal(a.sc, key, P);
+        const float3 Ng = geometric_normal(sc, key, P);
         N = dot(Ng, d) > 0.0f ? -1.0f * Ng : Ng;
         V = -1.0f * d;
         float4 m2;
-        material_of(a.sc, key, &m0, &m1, &m2);
-        add = mul(thr, mul(make_float3(a.sc.ambient[0], a.sc.ambient[1], a.sc.ambient[2]), f3(m0)));
+        material_of(sc, key, &m0, &m1, &m2);
+        add = mul(thr, mul(make_float3(sc.ambient[0], sc.ambient[1], sc.ambient[2]), f3(m0)));
         for (int l = 0; l < L; ++l) {
-          const float3 Lv = f3(a.sc.lights[2 * l]) - P;
+          const float3 Lv = f3(lights[2 * l]) - P;
           const float dist = sqrtf(dot(Lv, Lv));
           const float ndl = dot(N, (1.0f / dist) * Lv);
           if (dist > kSecondaryTmin && ndl > 0.0f) mask |= 1u << l;
         }
         kr3 = f3(m2);
-        if (may_reflect && (m2.x != 0.0f || m2.y != 0.0f || m2.z != 0.0f)) {
+        if (depth < it.cam.D && (m2.x != 0.0f || m2.y != 0.0f || m2.z != 0.0f)) {
           spawn = true;
           rdir = normalize(d - (2.0f * dot(d, N)) * N);
         }
@@ -586,15 +616,16 @@ __global__ __launch_bounds__(kBlock) void k_shade(KArgs a, int depth) {
         rad[1] += add.y;
         rad[2] += add.z;
       }
-      a.resinfo[q][e] = make_uint2(uint32_t(__float_as_int(ro.w)), mask);
+      a.resinfo[q][e] = make_uint2(lp, mask);
     }
-    // per-wave counts of every queue, then one atomic per block and queue
-    for (int l = 0; l <= L; ++l) {
-      const uint64_t bal = __ballot(l < L ? ((mask >> l) & 1u) != 0 : spawn);
+    // per-wave counts of every queue (light queues 0..LS-1, mirror queue LS), then one atomic per
+    // block and queue
+    for (int l = 0; l <= LS; ++l) {
+      const uint64_t bal = __ballot(l < LS ? ((mask >> l) & 1u) != 0 : spawn);
       if (lane == 0) wcnt[wave][l] = uint32_t(__popcll(bal));
     }
     __syncthreads();
-    if (threadIdx.x <= uint32_t(L)) {
+    if (threadIdx.x <= uint32_t(LS)) {
       const int l = threadIdx.x;
       uint32_t run = 0;
       for (int w = 0; w < kWaves; ++w) {
@@ -602,34 +633,34 @@ __global__ __launch_bounds__(kBlock) void k_shade(KArgs a, int depth) {
         wcnt[w][l] = run;
         run += c;
       }
-      uint32_t* ctr = l < L ? &a.ctr->shadow_count[depth][l] : &a.ctr->refl_count[depth + 1];
+      uint32_t* ctr = l < LS ? &a.ctr->shadow_count[depth][l] : &a.ctr->refl_count[depth + 1];
       bbase[l] = run ? atomicAdd(ctr, run) : 0u;
     }
     __syncthreads();
-    for (int l = 0; l < L; ++l) {
+    for (int l = 0; l < LS; ++l) {
       const bool mine = ((mask >> l) & 1u) != 0;
       const uint64_t bal = __ballot(mine);
       if (mine) {
         const uint32_t slot = bbase[l] + wcnt[wave][l] + uint32_t(__popcll(bal & lanemask_lt()));
-        const float3 Lv = f3(a.sc.lights[2 * l]) - P;
+        const float3 Lv = f3(lights[2 * l]) - P;
         const float dist = sqrtf(dot(Lv, Lv));
         const float3 Ld = (1.0f / dist) * Lv;
         const float ndl = dot(N, Ld);
         const float3 R = (2.0f * ndl) * N - Ld;
         const float rv = fmaxf(0.0f, dot(R, V));
         const float spec = powf(rv, m0.w);
-        const float3 I = f3(a.sc.lights[2 * l + 1]);
+        const float3 I = f3(lights[2 * l + 1]);
         const float3 term = mul(I, ndl * f3(m0) + spec * f3(m1));
         const size_t s = size_t(l) * a.cap + slot;
         a.srec[q][s] = make_float4(P.x, P.y, P.z, __int_as_float(key));
         a.sowner[q][s] = e;
-        a.contrib[q][size_t(e) * L + l] = make_float4(term.x * thr.x, term.y * thr.y, term.z * thr.z, 0.f);
+        a.contrib[q][size_t(e) * LS + l] = make_float4(term.x * thr.x, term.y * thr.y, term.z * thr.z, 0.f);
       }
     }
-    if (may_reflect) {
+    {
       const uint64_t bal = __ballot(spawn);
       if (spawn) {
-        const uint32_t slot = bbase[L] + wcnt[wave][L] + uint32_t(__popcll(bal & lanemask_lt()));
+        const uint32_t slot = bbase[LS] + wcnt[wave][LS] + uint32_t(__popcll(bal & lanemask_lt()));
         a.ro[nq][slot] = make_float4(P.x, P.y, P.z, ro.w);
         a.rd[nq][slot] = make_float4(rdir.x, rdir.y, rdir.z, __int_as_float(key));
         a.thr[nq][slot] = make_float4(thr.x * kr3.x, thr.y * kr3.y, thr.z * kr3.z, 0.f);
@@ -644,27 +675,29 @@ __global__ __launch_bounds__(kBlock) void k_shade(KArgs a, int depth) {
 }
 
 // k_resolve: adds the unoccluded lights' terms of depth `depth` to each path's pixel, in light order.
-template <bool PATH_IDS>
+template <bool PATH_IDS, bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_resolve(KArgs a, int depth) {
   const int q = depth & 1;
   const uint32_t total = depth == 0 ? uint32_t(a.path_count) : a.ctr->refl_count[depth];
-  const int L = a.sc.L;
-  const int D1 = a.cam.D + 1;
+  const int LS = a.lstride;
   for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < total; e += gridDim.x * kBlock) {
     const uint2 ri = a.resinfo[q][e];
     if (ri.y == 0) continue;  // no shadow rays (also invalid paths)
+    const int64_t p = a.path_begin + ri.x;
+    const DevItem& it = item_ref<MULTI>(a, item_of<MULTI>(a, p));
+    const int L = it.sc.L, D1 = it.cam.D + 1;
     int eye, x, y;
-    path_pixel(a.cam, int64_t(ri.x), &eye, &x, &y);
-    const int64_t pix = int64_t(y) * a.cam.W + x;
+    path_pixel(it.cam, p - it.path_offset, &eye, &x, &y);
+    const int64_t pix = int64_t(y) * it.cam.W + x;
     float3 sum = make_float3(0.f, 0.f, 0.f);
     for (int l = 0; l < L; ++l) {
       if (!((ri.y >> l) & 1u)) continue;
-      const size_t k = size_t(e) * L + l;
+      const size_t k = size_t(e) * LS + l;
       const bool v = a.vis[q][k] != 0;
       if (v) sum = sum + f3(a.contrib[q][k]);
-      if (PATH_IDS) a.shadow_state[eye][(pix * D1 + depth) * L + l] = v ? 2 : 1;
+      if (PATH_IDS) it.out.shadow_state[eye][(pix * D1 + depth) * L + l] = v ? 2 : 1;
     }
-    float* rad = a.radiance[eye] + 3 * pix;
+    float* rad = it.out.radiance[eye] + 3 * pix;
     rad[0] += sum.x;
     rad[1] += sum.y;
     rad[2] += sum.z;
@@ -741,7 +774,8 @@ int trace_grid_size(int device) {
   int grid = kMaxTraceBlocks;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<false>, kBlock, 0) != hipSuccess || per_cu <= 0)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<false, false>, kBlock, 0) != hipSuccess ||
+        per_cu <= 0)
       per_cu = 4;
     grid = std::min(kMaxTraceBlocks, prop.multiProcessorCount * per_cu);
   }
@@ -779,8 +813,12 @@ size_t plan_render(int64_t chunk, int32_t L, int grid_trace, RenderPlan* p) {
 
 hipError_t render_chunk(const RenderArgs& ra, hipStream_t s, TimerImpl* timer) {
   KArgs a{};
-  a.sc = ra.scene;
-  a.cam = ra.cam;
+  const bool multi = ra.items != nullptr;
+  a.one = ra.one;
+  a.items = ra.items;
+  a.num_items = multi ? ra.num_items : 1;
+  a.lstride = std::max(ra.max_lights, 1);
+  a.dmax = ra.max_depth;
   char* ws = ra.ws;
   const RenderPlan& p = ra.plan;
   a.ctr = reinterpret_cast<Counters*>(ws + p.counters_off);
@@ -796,17 +834,8 @@ hipError_t render_chunk(const RenderArgs& ra, hipStream_t s, TimerImpl* timer) {
   }
   a.hit = reinterpret_cast<float2*>(ws + p.hit_off);
   a.gstack = reinterpret_cast<uint32_t*>(ws + p.gstack_off);
-  const rt_stereo_output* o = ra.out;
-  const bool ids = (ra.flags & RT_FLAG_PATH_IDS) && o->path_prims[0] && o->path_prims[1] && o->shadow_state[0] &&
-                   o->shadow_state[1];
+  const bool ids = (ra.flags & RT_FLAG_PATH_IDS) != 0;
   const bool count = (ra.flags & RT_FLAG_COUNT_WORK) != 0;
-  for (int e = 0; e < 2; ++e) {
-    a.radiance[e] = o->radiance[e];
-    a.hit_t[e] = o->hit_t[e];
-    a.hit_prim[e] = o->hit_prim[e];
-    a.path_prims[e] = ids ? o->path_prims[e] : nullptr;
-    a.shadow_state[e] = ids ? o->shadow_state[e] : nullptr;
-  }
   a.path_begin = ra.path_begin;
   a.path_count = ra.path_count;
   a.cap = uint32_t(p.chunk_paths);
@@ -821,27 +850,66 @@ hipError_t render_chunk(const RenderArgs& ra, hipStream_t s, TimerImpl* timer) {
   e = hipGetLastError();
   if (timer) timer_end(timer, RT_STAGE_SETUP, s);
   if (e != hipSuccess) return e;
-  const int D = a.cam.D;
+  const int D = a.dmax;
   for (int d = 0; d <= D + 1; ++d) {
-    e = count ? launch(k_trace<true>, gtrace, a, d, s, timer, RT_STAGE_TRACE)
-              : launch(k_trace<false>, gtrace, a, d, s, timer, RT_STAGE_TRACE);
+    if (multi)
+      e = count ? launch(k_trace<true, true>, gtrace, a, d, s, timer, RT_STAGE_TRACE)
+                : launch(k_trace<false, true>, gtrace, a, d, s, timer, RT_STAGE_TRACE);
+    else
+      e = count ? launch(k_trace<true, false>, gtrace, a, d, s, timer, RT_STAGE_TRACE)
+                : launch(k_trace<false, false>, gtrace, a, d, s, timer, RT_STAGE_TRACE);
     if (e != hipSuccess) return e;
     if (d <= D) {
-      e = ids ? launch(k_shade<true>, gstream, a, d, s, timer, RT_STAGE_SHADE)
-              : launch(k_shade<false>, gstream, a, d, s, timer, RT_STAGE_SHADE);
+      if (multi)
+        e = ids ? launch(k_shade<true, true>, gstream, a, d, s, timer, RT_STAGE_SHADE)
+                : launch(k_shade<false, true>, gstream, a, d, s, timer, RT_STAGE_SHADE);
+      else
+        e = ids ? launch(k_shade<true, false>, gstream, a, d, s, timer, RT_STAGE_SHADE)
+                : launch(k_shade<false, false>, gstream, a, d, s, timer, RT_STAGE_SHADE);
       if (e != hipSuccess) return e;
     }
     if (d >= 1) {
-      e = ids ? launch(k_resolve<true>, gstream, a, d - 1, s, timer, RT_STAGE_RESOLVE)
-              : launch(k_resolve<false>, gstream, a, d - 1, s, timer, RT_STAGE_RESOLVE);
+      if (multi)
+        e = ids ? launch(k_resolve<true, true>, gstream, a, d - 1, s, timer, RT_STAGE_RESOLVE)
+                : launch(k_resolve<false, true>, gstream, a, d - 1, s, timer, RT_STAGE_RESOLVE);
+      else
+        e = ids ? launch(k_resolve<true, false>, gstream, a, d - 1, s, timer, RT_STAGE_RESOLVE)
+                : launch(k_resolve<false, false>, gstream, a, d - 1, s, timer, RT_STAGE_RESOLVE);
       if (e != hipSuccess) return e;
     }
   }
-  if (o->ray_counts) {
-    k_finish<<<1, 64, 0, s>>>(a.ctr, D, a.sc.L, o->ray_counts);
+  if (ra.ray_counts) {
+    k_finish<<<1, 64, 0, s>>>(a.ctr, D, a.lstride, ra.ray_counts);
     e = hipGetLastError();
   }
   return e;
+}
+
+// The item table is written by a kernel whose arguments carry up to kItemsPerUpload items, so a
+// batch needs no host staging buffer and can be captured into a graph.
+namespace {
+constexpr int kItemsPerUpload = 8;
+struct ItemUpload {
+  DevItem items[kItemsPerUpload];
+  int32_t n;
+};
+static_assert(sizeof(ItemUpload) <= 4000, "kernel argument block too large");
+__global__ void k_upload_items(ItemUpload u, DevItem* dst) {
+  const int i = threadIdx.x;
+  if (i < u.n) dst[i] = u.items[i];
+}
+}  // namespace
+
+hipError_t upload_items(const DevItem* items, int n, DevItem* dst, hipStream_t s) {
+  for (int i = 0; i < n; i += kItemsPerUpload) {
+    ItemUpload u{};
+    u.n = std::min(kItemsPerUpload, n - i);
+    for (int k = 0; k < u.n; ++k) u.items[k] = items[i + k];
+    k_upload_items<<<1, kItemsPerUpload, 0, s>>>(u, dst + i);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace srt

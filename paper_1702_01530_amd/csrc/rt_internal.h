@@ -72,6 +72,23 @@ struct DevCamera {
   int32_t tiles_x, tiles_y;
 };
 
+// Output pointers of one stereo render (device; optional ones may be null).
+struct DevOutputs {
+  float* radiance[2];
+  float* hit_t[2];
+  int32_t* hit_prim[2];
+  int32_t* path_prims[2];
+  uint8_t* shadow_state[2];
+};
+
+// One render of a batch: its scene, camera, outputs, and where its paths start in the batch's path space.
+struct DevItem {
+  DevScene sc;
+  DevCamera cam;
+  DevOutputs out;
+  int64_t path_offset;
+};
+
 // Work counters inside the render workspace.
 struct Counters {
   uint32_t refl_count[RT_MAX_DEPTH + 2];                   // entries of the mirror-ray queue at depth d
@@ -136,18 +153,24 @@ void timer_begin(TimerImpl* t, int stage, hipStream_t s);
 void timer_end(TimerImpl* t, int stage, hipStream_t s);
 
 struct RenderArgs {
-  DevScene scene;
-  DevCamera cam;
-  const rt_stereo_output* out;
+  // single render: `one` (kernels keep its scene and camera in scalar registers)
+  // batch: `items` (device table of num_items entries; each ray finds its item by path id)
+  DevItem one;
+  const DevItem* items;
+  int32_t num_items;
+  int32_t max_lights, max_depth;
+  int64_t* ray_counts;  // device, optional
   uint32_t flags;
   char* ws;
   RenderPlan plan;
-  int64_t path_begin, path_count;
+  int64_t path_begin, path_count;  // this pass's range of the (batch's) path space
 };
+
+// Writes `n` items into the device table at `dst` (stream-ordered, no host staging).
+hipError_t upload_items(const DevItem* items, int n, DevItem* dst, hipStream_t stream);
 
 hipError_t render_chunk(const RenderArgs& a, hipStream_t stream, TimerImpl* timer);
 // Copies `bytes` (a multiple of 4) from device memory into pinned host memory through its device view.
 hipError_t copy_to_host(const void* src, void* host_dst_device_view, size_t bytes, int blocks, hipStream_t s);
-hipError_t add_ray_counts(const RenderArgs& a, hipStream_t stream);
 
 }  // namespace srt

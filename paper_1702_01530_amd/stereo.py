@@ -147,6 +147,27 @@ def render_stereo(gs: GpuScene, cam, *, path_ids=False, count_work=False, brute_
     return o
 
 
+def render_batch(pairs, *, path_ids=False, count_work=False, brute_force=False, host=False,
+                 workspace: Workspace | None = None, outputs: list | None = None, stream=None, timer=None,
+                 readback_memcpy=False) -> list:
+    """Renders a batch of (GpuScene, camera) pairs as one pipeline; returns one output dict per pair.
+    The batch's total ray counts go to the first pair's ``ray_counts``."""
+    flags = (rt.RT_FLAG_PATH_IDS if path_ids else 0) | (rt.RT_FLAG_COUNT_WORK if count_work else 0) | (
+        rt.RT_FLAG_BRUTE_FORCE if brute_force else 0) | (rt.RT_FLAG_READBACK_MEMCPY if readback_memcpy else 0)
+    n = len(pairs)
+    items = (rt.rt_batch_item * n)()
+    outs = outputs if outputs is not None else [
+        alloc_outputs(cam, gs.num_lights, gs.device, path_ids, host, counts=(i == 0)) for i, (gs, cam) in enumerate(pairs)]
+    for i, (gs, cam) in enumerate(pairs):
+        items[i].scene = gs.handle
+        items[i].camera = rt.make_camera_struct(cam)
+        items[i].out = output_struct(outs[i])
+    if workspace is None:
+        workspace = Workspace(rt.rt_render_batch_workspace_size(items), pairs[0][0].device)
+    rt.rt_render_batch(items, workspace.ptr, workspace.nbytes, flags, stream_handle(stream), timer)
+    return outs
+
+
 class Timer:
     def __init__(self):
         self.handle = rt.rt_timer_create()

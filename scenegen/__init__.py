@@ -433,6 +433,38 @@ def make_small_terrain(seed: int = 11, grid: int = 24, n_spheres: int = 4, level
     return scene, cam
 
 
+def make_batch_workload(seed: int = 4, n_pairs: int = 64, n_scenes: int = 8, t_min=1_000, t_max=500_000):
+    """Batched rendering: n_pairs stereo pairs over n_scenes resident scenes whose triangle counts are
+    log-uniform in [t_min, t_max] (terrain + icosphere scenes like the 212k workload), resolutions
+    drawn from {320x240, 640x480, 1280x720, 1920x1080}, baselines U[0.03, 0.1], camera poses on seeded
+    orbits around each scene, reflection depth 1-3, 2 lights.  Returns (scenes, [(scene index, camera)])."""
+    g, _m, _mir, _li, cam_rng = _streams(seed)
+    targets = np.exp(np.linspace(np.log(t_min), np.log(t_max), n_scenes))
+    scenes = []
+    for k, tgt in enumerate(targets):
+        level = 1 if tgt < 5_000 else (2 if tgt < 50_000 else 3)
+        per_sphere = 20 * 4 ** level
+        n_sph = int(max(2, min(64, round(0.35 * tgt / per_sphere))))
+        grid = int(max(6, round(np.sqrt(max(tgt - n_sph * per_sphere, 50) / 2.0)) + 1))
+        sc = make_terrain_scene(seed * 100 + k, grid=grid, extent=16.0, octaves=6, base_freq=0.25,
+                                n_spheres=n_sph, level=level, radius=(0.3, 0.8),
+                                lights=[[-6, 8, 2, 0.7, 0.7, 0.7], [6, 6, 12, 0.7, 0.7, 0.7]], name=f"batch{k}")
+        scenes.append(sc)
+    sizes = [(320, 240), (640, 480), (1280, 720), (1920, 1080)]
+    pairs = []
+    for i in range(n_pairs):
+        k = int(cam_rng.integers(n_scenes))
+        w, h = sizes[int(cam_rng.integers(len(sizes)))]
+        ang = cam_rng.uniform(0, 2 * np.pi)
+        rad = cam_rng.uniform(7.0, 11.0)
+        centre = np.array([0.0, 0.0, 8.0])
+        eye = centre + np.array([rad * np.sin(ang), cam_rng.uniform(2.0, 4.0), -rad * np.cos(ang)])
+        cam = make_camera(eye, target=centre, baseline=cam_rng.uniform(0.03, 0.1), width=w, height=h,
+                          max_depth=int(cam_rng.integers(1, 4)))
+        pairs.append((k, cam))
+    return scenes, pairs
+
+
 WORKLOADS = {
     "spheres8_256": make_spheres_scene,
     "paper5": make_paper5_scene,

@@ -106,6 +106,41 @@ def test_chunking_and_repeat_bitwise(torch_cuda):
     gs.close()
 
 
+def test_batch_equals_single_renders(torch_cuda):
+    """A batch mixing scenes (with and without spheres/planes), resolutions, depths and light counts gives
+    every item exactly its standalone render, with one pass and with many small passes."""
+    torch = torch_cuda
+    from paper_1702_01530_amd import rt
+    from paper_1702_01530_amd.stereo import GpuScene, Workspace, render_batch, render_stereo
+    s1, c1 = sg.make_small_terrain(seed=5, grid=20, n_spheres=3, level=1, lights=2, depth=3)
+    s2, c2 = sg.make_spheres_scene()
+    s3, c3 = sg.make_small_terrain(seed=9, grid=30, n_spheres=4, level=2, lights=4, depth=2)
+    s4, c4 = sg.make_paper5_scene()
+    g = [GpuScene(x) for x in (s1, s2, s3, s4)]
+    pairs = [(g[0], c1.resized(40, 24)), (g[1], c2.resized(64, 48)), (g[2], c3.resized(77, 45)),
+             (g[3], c4.resized(33, 17)), (g[0], c1.resized(96, 64).with_(max_depth=1)),
+             (g[1], c2.resized(23, 71).with_(max_depth=0))]
+    single = [render_stereo(gs, cam, path_ids=True) for gs, cam in pairs]
+    batched = render_batch(pairs, path_ids=True)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(single, batched)):
+        for k in ("radiance", "hit_t", "hit_prim", "path_prims"):
+            assert torch.equal(a[k], b[k]), (i, k)
+        L = pairs[i][0].num_lights
+        assert torch.equal(a["shadow_state"][..., :L], b["shadow_state"][..., :L]), i
+    total = sum(int(o["ray_counts"][0]) for o in single)
+    assert int(batched[0]["ray_counts"][0]) == total
+    # a workspace a little above the minimum: passes that straddle item boundaries
+    need_min = rt.rt_render_workspace_min(4) + 4096
+    multi = render_batch(pairs, path_ids=True, workspace=Workspace(need_min))
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(single, multi)):
+        for k in ("radiance", "hit_t", "hit_prim", "path_prims"):
+            assert torch.equal(a[k], b[k]), (i, k, "small workspace")
+    for x in g:
+        x.close()
+
+
 def test_degenerate_scenes(torch_cuda):
     torch = torch_cuda
     bg = (0.25, 0.5, 0.75)
