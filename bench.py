@@ -117,8 +117,15 @@ def bench_batch(args):
     def batched():
         render_batch(pairs, outputs=outs, workspace=ws_batch)
 
+    from paper_1702_01530_amd.stereo import BatchGraph, autotune_batch
+    stream = torch.cuda.current_stream()
+    graph = BatchGraph(pairs, outs, ws_batch, stream=stream)
+
+    def graphed():
+        graph.launch(pairs, outs)
+
     res = {}
-    for name, fn in (("per_frame", per_frame), ("batched", batched)):
+    for name, fn in (("per_frame", per_frame), ("batched", batched), ("graph", graphed)):
         for _ in range(max(1, args.warmup)):
             fn()
         torch.cuda.synchronize()
@@ -132,14 +139,33 @@ def bench_batch(args):
         res[name] = {"ms_per_batch": ms, "stereo_fps": len(pairs) / (ms * 1e-3), "mrays_s": rays / (ms * 1e-3) / 1e6}
         log(f"[batch] {name}: {ms:.2f} ms per 64 pairs = {res[name]['stereo_fps']:.1f} stereo frames/s, "
             f"{res[name]['mrays_s']:.0f} Mrays/s")
+    t0 = time.perf_counter()
+    tuning, tuned_ms = autotune_batch(pairs, outs, ws_batch, repeats=1)
+    log(f"[batch] autotune ({time.perf_counter() - t0:.1f} s): {tuning} -> {tuned_ms:.2f} ms per batch")
+    graph.close()
+    graph = BatchGraph(pairs, outs, ws_batch, stream=stream)  # recaptured with the tuned launch shape
+    for name, fn in (("batched_tuned", batched), ("graph_tuned", graphed)):
+        fn()
+        torch.cuda.synchronize()
+        t0e, t1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0e.record()
+        for _ in range(args.steps):
+            fn()
+        t1e.record()
+        torch.cuda.synchronize()
+        ms = t0e.elapsed_time(t1e) / args.steps
+        res[name] = {"ms_per_batch": ms, "stereo_fps": len(pairs) / (ms * 1e-3), "mrays_s": rays / (ms * 1e-3) / 1e6}
+        log(f"[batch] {name}: {ms:.2f} ms per 64 pairs = {res[name]['stereo_fps']:.1f} stereo frames/s")
+    graph.close()
+    best = min(("batched", "graph", "batched_tuned", "graph_tuned"), key=lambda k: res[k]["ms_per_batch"])
     out = {"metric": "stereo frames/s, batched vs per-frame (64 mixed pairs, 8 resident scenes)",
-           "value": res["batched"]["stereo_fps"], "unit": "stereo frames/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": res["batched"]["ms_per_batch"], "higher_is_better": True,
+           "value": res[best]["stereo_fps"], "unit": "stereo frames/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res[best]["ms_per_batch"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batch64", "pairs": len(pairs), "scenes": len(scenes), "paths": paths,
                       "rays_per_batch": rays},
-           "batched": res["batched"], "per_frame": res["per_frame"],
-           "speedup": res["per_frame"]["ms_per_batch"] / res["batched"]["ms_per_batch"]}
+           "modes": res, "best_mode": best, "tuning": tuning,
+           "speedup": res["per_frame"]["ms_per_batch"] / res[best]["ms_per_batch"]}
     for g in gss:
         g.close()
     print(json.dumps(out), flush=True)
@@ -184,7 +210,8 @@ def main():
 
     rt.lib()
     if args.workload == "batch64":
-        return bench_batch(args)
+        with torch.cuda.stream(torch.cuda.Stream()):  # graph capture needs a stream other than the null stream
+            return bench_batch(args)
     scene, cam = workload(args.workload)
     log(f"[bench] workload {args.workload}: {scene.num_triangles} triangles, {cam.width}x{cam.height} per eye, "
         f"depth {cam.max_depth}, {scene.num_lights} lights")

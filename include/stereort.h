@@ -236,6 +236,40 @@ rt_status rt_render_batch_workspace_size(const rt_batch_item* items, int32_t n, 
 rt_status rt_render_batch(const rt_batch_item* items, int32_t n, void* workspace, size_t workspace_bytes,
                           uint32_t flags, void* stream, rt_timer timer);
 
+/* Graph capture of a batch: the render passes of a batch are captured once
+ * into a HIP graph and replayed by rt_batch_graph_launch for later batches of
+ * the same shape (item count, and per item width, height, max_depth and light
+ * count; the scenes, poses, baselines and outputs may change).  Each launch
+ * re-uploads the item table outside the graph, replays the graph on `stream`
+ * and reads back host_radiance buffers.  The workspace and flags are fixed at
+ * capture; items[0].out.ray_counts must stay the same pointer.  Capture
+ * enqueues the item-table upload on `stream`, then records the passes without
+ * running them. */
+typedef struct rt_batch_graph_s* rt_batch_graph;
+rt_status rt_batch_graph_create(const rt_batch_item* items, int32_t n, void* workspace, size_t workspace_bytes,
+                                uint32_t flags, void* stream, rt_batch_graph* out);
+rt_status rt_batch_graph_launch(rt_batch_graph graph, const rt_batch_item* items, int32_t n, void* stream);
+rt_status rt_batch_graph_destroy(rt_batch_graph graph);
+
+/* Launch tuning (process-wide).  Results are identical for every setting; only
+ * speed changes.  trace_blocks_per_cu: persistent traversal workgroups per CU
+ * (0 = as many as fit); stream_blocks: workgroups of the shading launches;
+ * max_pass_paths: largest number of paths per pass (>= 4096). */
+typedef struct {
+  int32_t trace_blocks_per_cu;
+  int32_t stream_blocks;
+  int64_t max_pass_paths;
+} rt_tuning;
+rt_status rt_get_tuning(rt_tuning* out);
+rt_status rt_set_tuning(const rt_tuning* tuning);
+
+/* Autotuner: renders the batch (with `repeats` timed repetitions) under each
+ * candidate tuning, keeps the fastest, installs it with rt_set_tuning and
+ * returns it (and its time per batch in ms).  Blocks until done; the batch's
+ * outputs hold a normal render afterwards. */
+rt_status rt_autotune_batch(const rt_batch_item* items, int32_t n, void* workspace, size_t workspace_bytes,
+                            uint32_t flags, void* stream, int32_t repeats, rt_tuning* best, double* best_ms);
+
 /* ---------------------------------------------------------------------------------------------
  * Per-kernel timing (the paper's per-stage time accounting, Section 4)
  * ------------------------------------------------------------------------------------------- */

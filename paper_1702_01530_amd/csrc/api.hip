@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -77,6 +78,15 @@ struct rt_timer_s : srt::TimerImpl {};
 namespace {
 
 thread_local std::string g_error;
+
+// Launch tuning (process-wide): results never depend on it, only speed does.
+std::mutex g_tuning_mutex;
+rt_tuning g_tuning = {0, 2048, int64_t(1) << 25};
+
+rt_tuning current_tuning() {
+  std::lock_guard<std::mutex> lock(g_tuning_mutex);
+  return g_tuning;
+}
 
 rt_status fail(rt_status s, const char* fmt, ...) {
   char buf[512];
@@ -181,7 +191,8 @@ constexpr int64_t kMaxChunk = int64_t(1) << 25;
 
 // Largest pass size (multiple of a tile pair) whose workspace fits `bytes`.
 int64_t chunk_for(int64_t total, int32_t L, size_t bytes, srt::RenderPlan* plan) {
-  int64_t hi_tiles = std::min(total, kMaxChunk) / srt::kPathsPerTile;
+  const int64_t cap = std::max<int64_t>(kMinChunk, std::min(kMaxChunk, current_tuning().max_pass_paths));
+  int64_t hi_tiles = std::max<int64_t>(1, std::min(total, cap) / srt::kPathsPerTile);
   int64_t lo_tiles = std::min<int64_t>(kMinChunk / srt::kPathsPerTile, hi_tiles);
   if (srt::plan_render(lo_tiles * srt::kPathsPerTile, L, 0, plan) > bytes) return 0;
   while (lo_tiles < hi_tiles) {
@@ -283,8 +294,10 @@ rt_status render_one(const rt_scene_s* scene, const rt_stereo_camera* cam, const
   if (st != RT_OK) return st;
   if (dev != scene->device)
     return fail(RT_ERR_INVALID_ARGUMENT, "scene was built on device %d, current device is %d", scene->device, dev);
-  plan.grid_trace = srt::trace_grid_size(dev);
+  const rt_tuning tune = current_tuning();
+  plan.grid_trace = srt::trace_grid_size(dev, tune.trace_blocks_per_cu, false);
   srt::RenderArgs ra{};
+  ra.stream_blocks = tune.stream_blocks;
   ra.one.sc = scene->dev;
   ra.one.cam = make_dev_camera(cam);
   ra.one.out = dev_outputs(out, flags);
@@ -308,7 +321,91 @@ rt_status render_one(const rt_scene_s* scene, const rt_stereo_camera* cam, const
 
 size_t batch_table_bytes(int32_t n) { return (size_t(n) * sizeof(srt::DevItem) + 255) & ~size_t(255); }
 
+struct BatchPlan {
+  std::vector<srt::DevItem> table;
+  std::vector<int64_t> shape;  // item count, then per item: width, height, depth, lights
+  srt::DevItem* dtable = nullptr;
+  srt::RenderArgs ra{};
+  int64_t total = 0, chunk = 0;
+};
+
+rt_status prepare_batch(const rt_batch_item* items, int32_t n, void* workspace, size_t workspace_bytes,
+                        uint32_t flags, BatchPlan* bp) {
+  if (n < 1 || !items) return fail(RT_ERR_INVALID_ARGUMENT, "bad batch arguments");
+  if (flags & ~kKnownFlags) return fail(RT_ERR_INVALID_ARGUMENT, "unknown render flags 0x%x", flags);
+  if (!workspace || !aligned256(workspace))
+    return fail(RT_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");
+  int dev = 0;
+  rt_status st = current_device(&dev);
+  if (st != RT_OK) return st;
+  bp->table.assign(static_cast<size_t>(n), srt::DevItem{});
+  bp->shape.assign(1, n);
+  int32_t lmax = 0, dmax = 0;
+  int64_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    const rt_batch_item& it = items[i];
+    if (!it.scene) return fail(RT_ERR_INVALID_ARGUMENT, "item %d has no scene", i);
+    if (it.scene->device != dev)
+      return fail(RT_ERR_INVALID_ARGUMENT, "item %d's scene was built on device %d, current device is %d", i,
+                  it.scene->device, dev);
+    if ((st = validate_camera(&it.camera)) != RT_OK) return st;
+    if ((st = check_output(&it.out, flags)) != RT_OK) return st;
+    srt::DevItem& d = bp->table[size_t(i)];
+    d.sc = it.scene->dev;
+    d.cam = make_dev_camera(&it.camera);
+    d.out = dev_outputs(&it.out, flags);
+    d.path_offset = total;
+    total += total_paths(&it.camera);
+    lmax = std::max(lmax, it.scene->dev.L);
+    dmax = std::max(dmax, it.camera.max_depth);
+    bp->shape.insert(bp->shape.end(), {it.camera.width, it.camera.height, it.camera.max_depth, it.scene->dev.L});
+  }
+  if (total >= (int64_t(1) << 31)) return fail(RT_ERR_UNSUPPORTED, "a batch is limited to 2^31 paths");
+  const size_t tbytes = batch_table_bytes(n);
+  if (workspace_bytes <= tbytes) return fail(RT_ERR_BUFFER_TOO_SMALL, "workspace smaller than the item table");
+  srt::RenderPlan plan;
+  const int64_t chunk = chunk_for(total, lmax, workspace_bytes - tbytes, &plan);
+  if (chunk == 0) return fail(RT_ERR_BUFFER_TOO_SMALL, "workspace of %zu bytes is too small", workspace_bytes);
+  const rt_tuning tune = current_tuning();
+  plan.grid_trace = srt::trace_grid_size(dev, tune.trace_blocks_per_cu, true);
+  char* ws = static_cast<char*>(workspace);
+  bp->dtable = reinterpret_cast<srt::DevItem*>(ws);
+  srt::RenderArgs& ra = bp->ra;
+  ra.items = bp->dtable;
+  ra.num_items = n;
+  ra.max_lights = lmax;
+  ra.max_depth = dmax;
+  ra.ray_counts = items[0].out.ray_counts;
+  ra.flags = flags;
+  ra.ws = ws + tbytes;
+  ra.plan = plan;
+  ra.stream_blocks = tune.stream_blocks;
+  bp->total = total;
+  bp->chunk = chunk;
+  return RT_OK;
+}
+
+rt_status run_batch_passes(BatchPlan& bp, hipStream_t stream, srt::TimerImpl* timer) {
+  for (int64_t begin = 0; begin < bp.total; begin += bp.chunk) {
+    bp.ra.path_begin = begin;
+    bp.ra.path_count = std::min(bp.chunk, bp.total - begin);
+    hipError_t e = srt::render_chunk(bp.ra, stream, timer);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  return RT_OK;
+}
+
 }  // namespace
+
+struct rt_batch_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int64_t> shape;
+  uint32_t flags = 0;
+  void* workspace = nullptr;
+  size_t workspace_bytes = 0;
+  int64_t* ray_counts = nullptr;
+};
 
 extern "C" {
 
@@ -482,63 +579,150 @@ rt_status rt_render_batch_workspace_size(const rt_batch_item* items, int32_t n, 
 
 rt_status rt_render_batch(const rt_batch_item* items, int32_t n, void* workspace, size_t workspace_bytes,
                           uint32_t flags, void* stream_in, rt_timer timer) {
-  if (n < 1 || !items) return fail(RT_ERR_INVALID_ARGUMENT, "bad batch arguments");
-  if (flags & ~kKnownFlags) return fail(RT_ERR_INVALID_ARGUMENT, "unknown render flags 0x%x", flags);
-  if (!workspace || !aligned256(workspace))
-    return fail(RT_ERR_INVALID_ARGUMENT, "workspace must be a 256-byte aligned device pointer");
-  int dev = 0;
-  rt_status st = current_device(&dev);
+  BatchPlan bp;
+  rt_status st = prepare_batch(items, n, workspace, workspace_bytes, flags, &bp);
   if (st != RT_OK) return st;
-  std::vector<srt::DevItem> table(static_cast<size_t>(n));
-  int64_t total = 0;
-  int32_t lmax = 0, dmax = 0;
-  for (int i = 0; i < n; ++i) {
-    const rt_batch_item& it = items[i];
-    if (!it.scene) return fail(RT_ERR_INVALID_ARGUMENT, "item %d has no scene", i);
-    if (it.scene->device != dev)
-      return fail(RT_ERR_INVALID_ARGUMENT, "item %d's scene was built on device %d, current device is %d", i,
-                  it.scene->device, dev);
-    if ((st = validate_camera(&it.camera)) != RT_OK) return st;
-    if ((st = check_output(&it.out, flags)) != RT_OK) return st;
-    srt::DevItem& d = table[size_t(i)];
-    d.sc = it.scene->dev;
-    d.cam = make_dev_camera(&it.camera);
-    d.out = dev_outputs(&it.out, flags);
-    d.path_offset = total;
-    total += total_paths(&it.camera);
-    lmax = std::max(lmax, it.scene->dev.L);
-    dmax = std::max(dmax, it.camera.max_depth);
-  }
-  if (total >= (int64_t(1) << 31)) return fail(RT_ERR_UNSUPPORTED, "a batch is limited to 2^31 paths");
-  const size_t tbytes = batch_table_bytes(n);
-  if (workspace_bytes <= tbytes) return fail(RT_ERR_BUFFER_TOO_SMALL, "workspace smaller than the item table");
-  srt::RenderPlan plan;
-  const int64_t chunk = chunk_for(total, lmax, workspace_bytes - tbytes, &plan);
-  if (chunk == 0) return fail(RT_ERR_BUFFER_TOO_SMALL, "workspace of %zu bytes is too small", workspace_bytes);
-  plan.grid_trace = srt::trace_grid_size(dev);
   hipStream_t stream = static_cast<hipStream_t>(stream_in);
-  char* ws = static_cast<char*>(workspace);
-  srt::DevItem* dtable = reinterpret_cast<srt::DevItem*>(ws);
-  hipError_t e = srt::upload_items(table.data(), n, dtable, stream);
+  hipError_t e = srt::upload_items(bp.table.data(), n, bp.dtable, stream);
   if (e != hipSuccess) return hip_fail(e, "item table upload");
-  srt::RenderArgs ra{};
-  ra.items = dtable;
-  ra.num_items = n;
-  ra.max_lights = lmax;
-  ra.max_depth = dmax;
-  ra.ray_counts = items[0].out.ray_counts;
-  ra.flags = flags;
-  ra.ws = ws + tbytes;
-  ra.plan = plan;
-  for (int64_t begin = 0; begin < total; begin += chunk) {
-    ra.path_begin = begin;
-    ra.path_count = std::min(chunk, total - begin);
-    e = srt::render_chunk(ra, stream, timer);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
-  }
+  if ((st = run_batch_passes(bp, stream, timer)) != RT_OK) return st;
   for (int i = 0; i < n; ++i)
     if ((st = readback(&items[i].camera, &items[i].out, flags, stream, nullptr, timer)) != RT_OK) return st;
   if (timer && timer->error != hipSuccess) return hip_fail(timer->error, "timer event");
+  return ok();
+}
+
+rt_status rt_batch_graph_create(const rt_batch_item* items, int32_t n, void* workspace, size_t workspace_bytes,
+                                uint32_t flags, void* stream_in, rt_batch_graph* out) {
+  if (!out) return fail(RT_ERR_INVALID_ARGUMENT, "graph pointer is NULL");
+  *out = nullptr;
+  if (flags & RT_FLAG_COUNT_WORK) return fail(RT_ERR_UNSUPPORTED, "RT_FLAG_COUNT_WORK is not captured into graphs");
+  BatchPlan bp;
+  rt_status st = prepare_batch(items, n, workspace, workspace_bytes, flags, &bp);
+  if (st != RT_OK) return st;
+  hipStream_t stream = static_cast<hipStream_t>(stream_in);
+  if (!stream) return fail(RT_ERR_INVALID_ARGUMENT, "graph capture needs a non-null stream");
+  hipError_t e = srt::upload_items(bp.table.data(), n, bp.dtable, stream);
+  if (e != hipSuccess) return hip_fail(e, "item table upload");
+  e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  st = run_batch_passes(bp, stream, nullptr);
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(stream, &graph);
+  if (st != RT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  rt_batch_graph_s* g = new (std::nothrow) rt_batch_graph_s();
+  if (!g) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return fail(RT_ERR_DEVICE, "out of host memory");
+  }
+  g->graph = graph;
+  g->exec = exec;
+  g->shape = bp.shape;
+  g->flags = flags;
+  g->workspace = workspace;
+  g->workspace_bytes = workspace_bytes;
+  g->ray_counts = items[0].out.ray_counts;
+  *out = g;
+  return ok();
+}
+
+rt_status rt_batch_graph_launch(rt_batch_graph g, const rt_batch_item* items, int32_t n, void* stream_in) {
+  if (!g) return fail(RT_ERR_INVALID_ARGUMENT, "graph is NULL");
+  BatchPlan bp;
+  rt_status st = prepare_batch(items, n, g->workspace, g->workspace_bytes, g->flags, &bp);
+  if (st != RT_OK) return st;
+  if (bp.shape != g->shape)
+    return fail(RT_ERR_INVALID_ARGUMENT, "the batch's shape (item count, sizes, depths, lights) differs from the "
+                                         "captured one");
+  if (items[0].out.ray_counts != g->ray_counts)
+    return fail(RT_ERR_INVALID_ARGUMENT, "items[0].out.ray_counts differs from the captured pointer");
+  hipStream_t stream = static_cast<hipStream_t>(stream_in);
+  hipError_t e = srt::upload_items(bp.table.data(), n, bp.dtable, stream);
+  if (e != hipSuccess) return hip_fail(e, "item table upload");
+  e = hipGraphLaunch(g->exec, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  for (int i = 0; i < n; ++i)
+    if ((st = readback(&items[i].camera, &items[i].out, g->flags, stream, nullptr, nullptr)) != RT_OK) return st;
+  return ok();
+}
+
+rt_status rt_batch_graph_destroy(rt_batch_graph g) {
+  if (!g) return fail(RT_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return ok();
+}
+
+rt_status rt_get_tuning(rt_tuning* out) {
+  if (!out) return fail(RT_ERR_INVALID_ARGUMENT, "tuning pointer is NULL");
+  *out = current_tuning();
+  return ok();
+}
+
+rt_status rt_set_tuning(const rt_tuning* t) {
+  if (!t) return fail(RT_ERR_INVALID_ARGUMENT, "tuning pointer is NULL");
+  if (t->trace_blocks_per_cu < 0 || t->trace_blocks_per_cu > 32 || t->stream_blocks < 1 ||
+      t->stream_blocks > (1 << 20) || t->max_pass_paths < kMinChunk)
+    return fail(RT_ERR_INVALID_ARGUMENT, "tuning out of range");
+  std::lock_guard<std::mutex> lock(g_tuning_mutex);
+  g_tuning = *t;
+  return ok();
+}
+
+rt_status rt_autotune_batch(const rt_batch_item* items, int32_t n, void* workspace, size_t workspace_bytes,
+                            uint32_t flags, void* stream_in, int32_t repeats, rt_tuning* best, double* best_ms) {
+  if (!best || repeats < 1) return fail(RT_ERR_INVALID_ARGUMENT, "bad autotune arguments");
+  hipStream_t stream = static_cast<hipStream_t>(stream_in);
+  const rt_tuning start = current_tuning();
+  const int per_cu_options[] = {0, 5, 4, 3, 2};
+  const int64_t pass_options[] = {int64_t(1) << 25, int64_t(1) << 23, int64_t(1) << 21};
+  const int stream_options[] = {2048, 8192};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(RT_ERR_DEVICE, "events");
+  double best_t = 1e300;
+  rt_tuning best_cfg = start;
+  rt_status st = RT_OK;
+  for (int pc : per_cu_options)
+    for (int64_t pp : pass_options)
+      for (int sb : stream_options) {
+        rt_tuning cand{pc, sb, pp};
+        if ((st = rt_set_tuning(&cand)) != RT_OK) break;
+        if ((st = rt_render_batch(items, n, workspace, workspace_bytes, flags, stream, nullptr)) != RT_OK) break;
+        (void)hipEventRecord(e0, stream);
+        for (int r = 0; r < repeats && st == RT_OK; ++r)
+          st = rt_render_batch(items, n, workspace, workspace_bytes, flags, stream, nullptr);
+        (void)hipEventRecord(e1, stream);
+        float ms = 0.f;
+        if (st != RT_OK || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          if (st == RT_OK) st = fail(RT_ERR_DEVICE, "autotune timing failed");
+          break;
+        }
+        if (ms / repeats < best_t) {
+          best_t = ms / repeats;
+          best_cfg = cand;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != RT_OK) {
+    rt_set_tuning(&start);
+    return st;
+  }
+  rt_set_tuning(&best_cfg);
+  *best = best_cfg;
+  if (best_ms) *best_ms = best_t;
   return ok();
 }
 

@@ -766,21 +766,27 @@ hipError_t copy_to_host(const void* src, void* host_dst_device_view, size_t byte
   return hipGetLastError();
 }
 
-int trace_grid_size(int device) {
-  static int cached[64] = {0};
+int trace_grid_size(int device, int blocks_per_cu, bool multi) {
+  static int cached_cus[64] = {0}, cached_occ[64][2] = {{0}};
   if (device < 0 || device >= 64) return kMaxTraceBlocks;
-  if (cached[device]) return cached[device];
-  hipDeviceProp_t prop;
-  int grid = kMaxTraceBlocks;
-  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace<false, false>, kBlock, 0) != hipSuccess ||
-        per_cu <= 0)
-      per_cu = 4;
-    grid = std::min(kMaxTraceBlocks, prop.multiProcessorCount * per_cu);
+  if (!cached_cus[device]) {
+    hipDeviceProp_t prop;
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
+    int occ[2] = {0, 0};
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], k_trace<false, false>, kBlock, 0) != hipSuccess ||
+        occ[0] <= 0)
+      occ[0] = 4;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], k_trace<false, true>, kBlock, 0) != hipSuccess ||
+        occ[1] <= 0)
+      occ[1] = 4;
+    cached_occ[device][0] = occ[0];
+    cached_occ[device][1] = occ[1];
+    cached_cus[device] = cus;
   }
-  cached[device] = grid;
-  return grid;
+  int per_cu = cached_occ[device][multi ? 1 : 0];
+  if (blocks_per_cu > 0) per_cu = std::min(per_cu, blocks_per_cu);
+  return std::min(kMaxTraceBlocks, cached_cus[device] * per_cu);
 }
 
 size_t plan_render(int64_t chunk, int32_t L, int grid_trace, RenderPlan* p) {
@@ -843,7 +849,8 @@ hipError_t render_chunk(const RenderArgs& ra, hipStream_t s, TimerImpl* timer) {
   a.trace_threads = p.grid_trace * kBlock;
 
   const unsigned gtrace = unsigned(p.grid_trace);
-  const unsigned gstream = unsigned(std::min<int64_t>((ra.path_count + kBlock - 1) / kBlock, 256 * 8));
+  const unsigned gstream =
+      unsigned(std::max<int64_t>(1, std::min<int64_t>((ra.path_count + kBlock - 1) / kBlock, ra.stream_blocks)));
   hipError_t e;
   if (timer) timer_begin(timer, RT_STAGE_SETUP, s);
   k_reset<<<1, 256, 0, s>>>(a.ctr);

@@ -145,7 +145,9 @@ struct RenderPlan {
   int grid_trace;  // persistent workgroups for the traversal kernels
 };
 
-int trace_grid_size(int device);
+// Persistent traversal workgroups: CUs x min(occupancy limit of the single or batch kernel,
+// blocks_per_cu if > 0).
+int trace_grid_size(int device, int blocks_per_cu, bool multi);
 size_t plan_render(int64_t chunk_paths, int32_t num_lights, int grid_trace, RenderPlan* plan);
 
 struct TimerImpl;
@@ -164,6 +166,7 @@ struct RenderArgs {
   char* ws;
   RenderPlan plan;
   int64_t path_begin, path_count;  // this pass's range of the (batch's) path space
+  int64_t stream_blocks;           // workgroups of the shading / resolve launches
 };
 
 // Writes `n` items into the device table at `dst` (stream-ordered, no host staging).

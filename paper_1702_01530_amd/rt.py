@@ -83,6 +83,10 @@ class rt_batch_item(C.Structure):
     _fields_ = [("scene", C.c_void_p), ("camera", rt_stereo_camera), ("out", rt_stereo_output)]
 
 
+class rt_tuning(C.Structure):
+    _fields_ = [("trace_blocks_per_cu", C.c_int32), ("stream_blocks", C.c_int32), ("max_pass_paths", C.c_int64)]
+
+
 class rt_timing(C.Structure):
     _fields_ = [("ms", C.c_double * RT_NUM_STAGES), ("launches", C.c_int64 * RT_NUM_STAGES)]
 
@@ -104,6 +108,14 @@ _SIGNATURES = {
     "rt_render_batch_workspace_size": (C.c_int, [C.POINTER(rt_batch_item), C.c_int32, C.POINTER(C.c_size_t)]),
     "rt_render_batch": (C.c_int, [C.POINTER(rt_batch_item), C.c_int32, C.c_void_p, C.c_size_t, C.c_uint32,
                                   C.c_void_p, C.c_void_p]),
+    "rt_batch_graph_create": (C.c_int, [C.POINTER(rt_batch_item), C.c_int32, C.c_void_p, C.c_size_t, C.c_uint32,
+                                        C.c_void_p, C.POINTER(C.c_void_p)]),
+    "rt_batch_graph_launch": (C.c_int, [C.c_void_p, C.POINTER(rt_batch_item), C.c_int32, C.c_void_p]),
+    "rt_batch_graph_destroy": (C.c_int, [C.c_void_p]),
+    "rt_get_tuning": (C.c_int, [C.POINTER(rt_tuning)]),
+    "rt_set_tuning": (C.c_int, [C.POINTER(rt_tuning)]),
+    "rt_autotune_batch": (C.c_int, [C.POINTER(rt_batch_item), C.c_int32, C.c_void_p, C.c_size_t, C.c_uint32,
+                                    C.c_void_p, C.c_int32, C.POINTER(rt_tuning), C.POINTER(C.c_double)]),
     "rt_timer_create": (C.c_int, [C.POINTER(C.c_void_p)]),
     "rt_timer_destroy": (C.c_int, [C.c_void_p]),
     "rt_timer_read": (C.c_int, [C.c_void_p, C.POINTER(rt_timing)]),
@@ -194,6 +206,39 @@ def rt_render_batch_workspace_size(items) -> int:
 
 def rt_render_batch(items, ws_ptr, ws_bytes, flags, stream, timer=None):
     check(lib().rt_render_batch(items, len(items), ws_ptr, ws_bytes, flags, stream, timer))
+
+
+def rt_batch_graph_create(items, ws_ptr, ws_bytes, flags, stream):
+    g = C.c_void_p()
+    check(lib().rt_batch_graph_create(items, len(items), ws_ptr, ws_bytes, flags, stream, C.byref(g)))
+    return g.value
+
+
+def rt_batch_graph_launch(graph, items, stream):
+    check(lib().rt_batch_graph_launch(graph, items, len(items), stream))
+
+
+def rt_batch_graph_destroy(graph):
+    check(lib().rt_batch_graph_destroy(graph))
+
+
+def rt_get_tuning() -> dict:
+    t = rt_tuning()
+    check(lib().rt_get_tuning(C.byref(t)))
+    return {k: getattr(t, k) for k, _ in rt_tuning._fields_}
+
+
+def rt_set_tuning(trace_blocks_per_cu=0, stream_blocks=2048, max_pass_paths=1 << 25):
+    t = rt_tuning(trace_blocks_per_cu, stream_blocks, max_pass_paths)
+    check(lib().rt_set_tuning(C.byref(t)))
+
+
+def rt_autotune_batch(items, ws_ptr, ws_bytes, flags, stream, repeats=2):
+    t = rt_tuning()
+    ms = C.c_double()
+    check(lib().rt_autotune_batch(items, len(items), ws_ptr, ws_bytes, flags, stream, repeats, C.byref(t),
+                                  C.byref(ms)))
+    return {k: getattr(t, k) for k, _ in rt_tuning._fields_}, ms.value
 
 
 def rt_timer_create():

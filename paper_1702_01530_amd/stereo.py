@@ -147,25 +147,74 @@ def render_stereo(gs: GpuScene, cam, *, path_ids=False, count_work=False, brute_
     return o
 
 
+def _flags(path_ids=False, count_work=False, brute_force=False, readback_memcpy=False) -> int:
+    return (rt.RT_FLAG_PATH_IDS if path_ids else 0) | (rt.RT_FLAG_COUNT_WORK if count_work else 0) | (
+        rt.RT_FLAG_BRUTE_FORCE if brute_force else 0) | (rt.RT_FLAG_READBACK_MEMCPY if readback_memcpy else 0)
+
+
+def batch_items(pairs, outs) -> C.Array:
+    items = (rt.rt_batch_item * len(pairs))()
+    for i, (gs, cam) in enumerate(pairs):
+        items[i].scene = gs.handle
+        items[i].camera = rt.make_camera_struct(cam)
+        items[i].out = output_struct(outs[i])
+    return items
+
+
+def batch_outputs(pairs, path_ids=False, host=False) -> list:
+    return [alloc_outputs(cam, gs.num_lights, gs.device, path_ids, host, counts=(i == 0))
+            for i, (gs, cam) in enumerate(pairs)]
+
+
 def render_batch(pairs, *, path_ids=False, count_work=False, brute_force=False, host=False,
                  workspace: Workspace | None = None, outputs: list | None = None, stream=None, timer=None,
                  readback_memcpy=False) -> list:
     """Renders a batch of (GpuScene, camera) pairs as one pipeline; returns one output dict per pair.
     The batch's total ray counts go to the first pair's ``ray_counts``."""
-    flags = (rt.RT_FLAG_PATH_IDS if path_ids else 0) | (rt.RT_FLAG_COUNT_WORK if count_work else 0) | (
-        rt.RT_FLAG_BRUTE_FORCE if brute_force else 0) | (rt.RT_FLAG_READBACK_MEMCPY if readback_memcpy else 0)
-    n = len(pairs)
-    items = (rt.rt_batch_item * n)()
-    outs = outputs if outputs is not None else [
-        alloc_outputs(cam, gs.num_lights, gs.device, path_ids, host, counts=(i == 0)) for i, (gs, cam) in enumerate(pairs)]
-    for i, (gs, cam) in enumerate(pairs):
-        items[i].scene = gs.handle
-        items[i].camera = rt.make_camera_struct(cam)
-        items[i].out = output_struct(outs[i])
+    flags = _flags(path_ids, count_work, brute_force, readback_memcpy)
+    outs = outputs if outputs is not None else batch_outputs(pairs, path_ids, host)
+    items = batch_items(pairs, outs)
     if workspace is None:
         workspace = Workspace(rt.rt_render_batch_workspace_size(items), pairs[0][0].device)
     rt.rt_render_batch(items, workspace.ptr, workspace.nbytes, flags, stream_handle(stream), timer)
     return outs
+
+
+class BatchGraph:
+    """A batch's render passes captured into a HIP graph; launch() replays them for any batch of the same
+    shape (item count, sizes, depths, light counts) with new scenes, poses and outputs."""
+
+    def __init__(self, pairs, outputs: list, workspace: Workspace, *, path_ids=False, readback_memcpy=False,
+                 stream=None):
+        self.flags = _flags(path_ids=path_ids, readback_memcpy=readback_memcpy)
+        self.workspace = workspace
+        self._stream = stream if stream is not None else torch.cuda.Stream()
+        items = batch_items(pairs, outputs)
+        self.handle = rt.rt_batch_graph_create(items, workspace.ptr, workspace.nbytes, self.flags,
+                                               self._stream.cuda_stream)
+
+    def launch(self, pairs, outputs: list, stream=None):
+        items = batch_items(pairs, outputs)
+        rt.rt_batch_graph_launch(self.handle, items, stream_handle(stream))
+        return outputs
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize()
+            rt.rt_batch_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_batch(pairs, outputs: list, workspace: Workspace, repeats=2, stream=None) -> tuple:
+    """Times the batch under each candidate launch tuning, installs the fastest and returns (tuning, ms)."""
+    items = batch_items(pairs, outputs)
+    return rt.rt_autotune_batch(items, workspace.ptr, workspace.nbytes, 0, stream_handle(stream), repeats)
 
 
 class Timer:

@@ -12,7 +12,7 @@ from paper_1702_01530_amd import rt
 def test_library_exports_every_declared_function():
     L = rt.lib()
     names = rt.header_functions()
-    assert len(names) >= 14
+    assert len(names) >= 20
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing
     assert set(names) == set(rt._SIGNATURES)
@@ -77,6 +77,19 @@ def test_camera_validation_and_workspace():
     bad = rt.make_camera_struct(cam.with_(forward=np.float32([0, 1, 0])))
     with pytest.raises(rt.RtError, match="parallel"):
         rt.rt_render_workspace_size(bad, 4)
+
+
+def test_tuning_validation():
+    saved = rt.rt_get_tuning()
+    assert saved["max_pass_paths"] >= 4096 and saved["stream_blocks"] >= 1
+    for bad in ({"trace_blocks_per_cu": -1}, {"stream_blocks": 0}, {"max_pass_paths": 100}):
+        args = dict(saved)
+        args.update(bad)
+        with pytest.raises(rt.RtError):
+            rt.rt_set_tuning(**args)
+    rt.rt_set_tuning(2, 512, 1 << 20)
+    assert rt.rt_get_tuning() == {"trace_blocks_per_cu": 2, "stream_blocks": 512, "max_pass_paths": 1 << 20}
+    rt.rt_set_tuning(**saved)
 
 
 def test_render_argument_checks_without_device():

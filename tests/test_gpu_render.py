@@ -141,6 +141,74 @@ def test_batch_equals_single_renders(torch_cuda):
         x.close()
 
 
+def test_batch_graph_replays_match_eager(torch_cuda):
+    """A captured batch replays bitwise like eager batches, with eager work and syncs between replays, and
+    accepts new poses of the same shape; a different shape is refused."""
+    torch = torch_cuda
+    from paper_1702_01530_amd import rt
+    from paper_1702_01530_amd.stereo import BatchGraph, GpuScene, Workspace, batch_items, batch_outputs, \
+        render_batch, render_stereo
+    s1, c1 = sg.make_small_terrain(seed=5, grid=20, n_spheres=3, level=1, lights=2, depth=3)
+    s2, c2 = sg.make_spheres_scene()
+    g1, g2 = GpuScene(s1), GpuScene(s2)
+    pairs_a = [(g1, c1.resized(40, 24)), (g2, c2.resized(64, 48))]
+    moved = c1.with_(center=np.float32(c1.center + np.array([0.3, 0.1, -0.2])), baseline=0.09)
+    pairs_b = [(g1, moved.resized(40, 24)), (g2, c2.resized(64, 48).with_(baseline=0.03))]
+    eager_a = render_batch(pairs_a, path_ids=True)
+    eager_b = render_batch(pairs_b, path_ids=True)
+    outs = batch_outputs(pairs_a, path_ids=True)
+    ws = Workspace(rt.rt_render_batch_workspace_size(batch_items(pairs_a, outs)))
+    stream = torch.cuda.Stream()
+    graph = BatchGraph(pairs_a, outs, ws, path_ids=True, stream=stream)
+    stream.synchronize()
+    for rep, (pairs, eager) in enumerate([(pairs_a, eager_a), (pairs_b, eager_b), (pairs_a, eager_a),
+                                          (pairs_b, eager_b)]):
+        for o in outs:
+            o["radiance"].fill_(-7.0)
+        render_stereo(g2, c2.resized(16, 16))  # eager work between replays
+        torch.cuda.synchronize()
+        graph.launch(pairs, outs, stream=stream)
+        stream.synchronize()
+        for i in range(2):
+            for k in ("radiance", "hit_t", "hit_prim", "path_prims"):
+                assert torch.equal(outs[i][k], eager[i][k]), (rep, i, k)
+    with pytest.raises(rt.RtError):
+        graph.launch([(g1, c1.resized(48, 24)), (g2, c2.resized(64, 48))], outs, stream=stream)
+    graph.close()
+    g1.close()
+    g2.close()
+
+
+def test_tuning_does_not_change_results(torch_cuda):
+    torch = torch_cuda
+    from paper_1702_01530_amd import rt
+    from paper_1702_01530_amd.stereo import GpuScene, Workspace, autotune_batch, batch_items, batch_outputs, \
+        render_batch
+    s1, c1 = sg.make_small_terrain(seed=8, grid=24, n_spheres=3, level=1, lights=2, depth=2)
+    g1 = GpuScene(s1)
+    pairs = [(g1, c1.resized(96, 64)), (g1, c1.resized(50, 30).with_(max_depth=1))]
+    ref = render_batch(pairs)
+    saved = rt.rt_get_tuning()
+    try:
+        for per_cu, passes in ((1, 4096), (3, 1 << 16), (0, 1 << 25)):
+            rt.rt_set_tuning(per_cu, 64, passes)
+            out = render_batch(pairs)
+            torch.cuda.synchronize()
+            for i in range(2):
+                assert torch.equal(out[i]["radiance"], ref[i]["radiance"]), (per_cu, passes, i)
+        outs = batch_outputs(pairs)
+        ws = Workspace(rt.rt_render_batch_workspace_size(batch_items(pairs, outs)))
+        best, ms = autotune_batch(pairs, outs, ws, repeats=1)
+        assert ms > 0 and best["max_pass_paths"] >= 4096
+        assert rt.rt_get_tuning() == best
+        torch.cuda.synchronize()
+        for i in range(2):
+            assert torch.equal(outs[i]["radiance"], ref[i]["radiance"])
+    finally:
+        rt.rt_set_tuning(**saved)
+    g1.close()
+
+
 def test_degenerate_scenes(torch_cuda):
     torch = torch_cuda
     bg = (0.25, 0.5, 0.75)
