@@ -171,6 +171,53 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args):
+    """Serving: Poisson arrivals over 8 resident scenes (10k-2M triangles), 640x480 to 3840x2160, depth 1-4.
+    Continuous batching (3 in-flight batch slots) versus one request at a time, on the same arrival trace."""
+    import numpy as np
+    import torch
+    import scenegen as sg
+    from paper_1702_01530_amd.serve import GpuRenderer, Request, Server, latency_stats
+    from paper_1702_01530_amd.stereo import GpuScene
+    scenes, trace = sg.make_serving_workload(n_requests=args.requests, rate_hz=args.rate)
+    gss = {k: GpuScene(s) for k, s in enumerate(scenes)}
+    log(f"[serve] {len(trace)} requests at {args.rate:.0f}/s over {len(scenes)} scenes "
+        f"({min(s.num_triangles for s in scenes)}-{max(s.num_triangles for s in scenes)} triangles)")
+    out = {}
+    for name, slots, max_batch in (("continuous_batching", 3, 64), ("one_at_a_time", 1, 1)):
+        rend = GpuRenderer(gss, slots=slots, workspace_bytes=6 << 30)
+        rend.prewarm(sorted({(c.width, c.height) for _, _, c in trace}), count=12)
+
+        def consume(req):  # the client takes the image, the pinned buffer goes back to the pool
+            if req.result is not None:
+                rend.release(req.result["radiance"])
+                req.result = None
+
+        server = Server(rend, hbm_budget=48 << 30, max_batch_paths=1 << 25, max_batch=max_batch, on_complete=consume)
+        server.run([(0.0, Request(-1 - i, k, cam)) for i, (_, k, cam) in enumerate(trace[:4])])  # warm-up
+        torch.cuda.synchronize()
+        server = Server(rend, hbm_budget=48 << 30, max_batch_paths=1 << 25, max_batch=max_batch, on_complete=consume)
+        done = server.run([(t, Request(i, k, cam)) for i, (t, k, cam) in enumerate(trace)])
+        st = latency_stats(done)
+        st["batches"] = server.batches
+        st["mean_batch"] = float(np.mean(server.batch_sizes)) if server.batch_sizes else 0.0
+        out[name] = st
+        log(f"[serve] {name}: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
+            f"{st['stereo_fps']:.1f} stereo frames/s, {st['batches']} batches (mean {st['mean_batch']:.1f})")
+        del rend, server
+        torch.cuda.synchronize()
+    res = {"metric": "p50/p99 latency and stereo frames/s served (Poisson arrivals)",
+           "value": out["continuous_batching"]["stereo_fps"], "unit": "stereo frames/s", "n_gpus": 1,
+           "steps": args.requests, "warmup": 4, "ms_per_step": 1e3 / out["continuous_batching"]["stereo_fps"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "serve", "requests": args.requests, "rate_hz": args.rate, "scenes": len(scenes)},
+           "p50_ms": out["continuous_batching"]["p50_ms"], "p99_ms": out["continuous_batching"]["p99_ms"],
+           "modes": out}
+    for g in gss.values():
+        g.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +225,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="terrain3.4M_1080p")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=200, help="serving workload: number of requests")
+    ap.add_argument("--rate", type=float, default=100.0, help="serving workload: Poisson arrival rate (1/s)")
     ap.add_argument("--no-end-to-end", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM traffic counters)")
@@ -209,6 +258,8 @@ def main():
         return
 
     rt.lib()
+    if args.workload == "serve":
+        return bench_serve(args)
     if args.workload == "batch64":
         with torch.cuda.stream(torch.cuda.Stream()):  # graph capture needs a stream other than the null stream
             return bench_batch(args)

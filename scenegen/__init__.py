@@ -465,6 +465,29 @@ def make_batch_workload(seed: int = 4, n_pairs: int = 64, n_scenes: int = 8, t_m
     return scenes, pairs
 
 
+def make_serving_workload(seed: int = 5, n_requests: int = 200, rate_hz: float = 100.0, n_scenes: int = 8,
+                          t_min=10_000, t_max=2_000_000, sizes=((640, 480), (1280, 720), (1920, 1080), (3840, 2160))):
+    """Serving: Poisson arrivals at `rate_hz` of requests (scene id, stereo camera) over n_scenes resident
+    scenes of log-uniform triangle counts in [t_min, t_max]; resolution drawn from `sizes`, baseline
+    U[0.03, 0.1], reflection depth 1-4, pose on a seeded orbit.  Returns (scenes, [(arrival s, scene, cam)])."""
+    scenes, _ = make_batch_workload(seed=seed, n_pairs=0, n_scenes=n_scenes, t_min=t_min, t_max=t_max)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed).spawn(6)[5]))
+    t = 0.0
+    reqs = []
+    for _ in range(n_requests):
+        t += rng.exponential(1.0 / rate_hz)
+        k = int(rng.integers(n_scenes))
+        w, h = sizes[int(rng.integers(len(sizes)))]
+        ang = rng.uniform(0, 2 * np.pi)
+        rad = rng.uniform(7.0, 11.0)
+        centre = np.array([0.0, 0.0, 8.0])
+        eye = centre + np.array([rad * np.sin(ang), rng.uniform(2.0, 4.0), -rad * np.cos(ang)])
+        cam = make_camera(eye, target=centre, baseline=rng.uniform(0.03, 0.1), width=w, height=h,
+                          max_depth=int(rng.integers(1, 5)))
+        reqs.append((t, k, cam))
+    return scenes, reqs
+
+
 WORKLOADS = {
     "spheres8_256": make_spheres_scene,
     "paper5": make_paper5_scene,

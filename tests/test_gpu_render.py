@@ -209,6 +209,34 @@ def test_tuning_does_not_change_results(torch_cuda):
     g1.close()
 
 
+def test_served_results_equal_standalone_renders(torch_cuda):
+    """Requests served in a mix (continuous batching over two in-flight slots) give exactly the image
+    each request gets when rendered alone."""
+    torch = torch_cuda
+    from paper_1702_01530_amd.serve import GpuRenderer, Request, Server, latency_stats
+    from paper_1702_01530_amd.stereo import GpuScene, render_stereo
+    s1, c1 = sg.make_small_terrain(seed=5, grid=20, n_spheres=3, level=1, lights=2, depth=3)
+    s2, c2 = sg.make_spheres_scene()
+    scenes = {"terrain": GpuScene(s1), "spheres": GpuScene(s2)}
+    rend = GpuRenderer(scenes, slots=2, workspace_bytes=512 << 20)
+    server = Server(rend, hbm_budget=64 << 20, max_batch_paths=1 << 16, max_batch=4)
+    specs = [("terrain", c1.resized(64, 40)), ("spheres", c2.resized(48, 48)), ("terrain", c1.resized(33, 17)),
+             ("spheres", c2.resized(80, 60).with_(max_depth=0)), ("terrain", c1.resized(96, 64)),
+             ("spheres", c2.resized(20, 90)), ("nope", c2), ("terrain", c1.with_(hfov_deg=200.0))]
+    arrivals = [(0.0005 * i, Request(i, sid, cam)) for i, (sid, cam) in enumerate(specs)]
+    done = {q.rid: q for q in server.run(arrivals, timeout_s=120)}
+    assert done[6].error and done[7].error  # unknown scene, invalid camera: failed alone
+    assert server.batches >= 2
+    for i, (sid, cam) in enumerate(specs[:6]):
+        assert done[i].error is None, done[i].error
+        alone = render_stereo(scenes[sid], cam, host=True)
+        torch.cuda.synchronize()
+        assert torch.equal(done[i].result["radiance"], alone["host_radiance"]), i
+    assert latency_stats(list(done.values()))["n"] == 6
+    for g in scenes.values():
+        g.close()
+
+
 def test_degenerate_scenes(torch_cuda):
     torch = torch_cuda
     bg = (0.25, 0.5, 0.75)
