@@ -218,6 +218,113 @@ def bench_serve(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_paper_shapes(args):
+    """The shapes of the paper's experiments (Section 4, Figs 3-8) measured on this GPU: synthesis time
+    against the number of objects and lights (brute force and LBVH), against the launch configuration,
+    and the split of a frame into computation, transfer and other time."""
+    import numpy as np
+    import torch
+    import scenegen as sg
+    from paper_1702_01530_amd import rt
+    from paper_1702_01530_amd.stereo import GpuScene, Workspace, alloc_outputs, render_stereo, Timer
+
+    def time_frames(gs, cam, n=5, **kw):
+        ws = Workspace.for_camera(cam, gs.num_lights)
+        out = alloc_outputs(cam, gs.num_lights, torch.device("cuda:0"))
+        render_stereo(gs, cam, workspace=ws, outputs=out, **kw)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            render_stereo(gs, cam, workspace=ws, outputs=out, **kw)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    res = {}
+    # (1) objects: the first k of the five-polyhedra scene (Fig. 6) plus a sixth solid, 1 light, 256x256 stereo
+    base, cam = sg.make_paper5_scene()
+    counts = np.cumsum([0] + [f for _, f in base.info["solids"]])
+    rows = []
+    for k in range(1, 6):
+        T = int(counts[k])
+        sc = sg.Scene(name=f"paper{k}", seed=6, triangles=base.triangles[:T], tri_material=base.tri_material[:T],
+                      spheres=base.spheres, sphere_material=base.sphere_material, planes=base.planes,
+                      plane_material=base.plane_material, materials=base.materials, lights=base.lights,
+                      ambient=base.ambient, background=base.background)
+        row = {"objects": k, "triangles": T}
+        for accel in ("none", "lbvh"):
+            gs = GpuScene(sc, accel=accel)
+            row[f"ms_{accel}"] = time_frames(gs, cam)
+            gs.close()
+        rows.append(row)
+        log(f"[shapes] {k} objects ({T} tris): brute {row['ms_none']:.3f} ms, lbvh {row['ms_lbvh']:.3f} ms")
+    res["objects"] = rows
+    # (2) polygon count: terrain scenes from 2k to 800k triangles, brute force while it stays cheap
+    rows = []
+    for grid in (24, 48, 96, 192, 384, 640):
+        sc, c2 = sg.make_small_terrain(seed=21, grid=grid, n_spheres=4, level=2, lights=1, depth=1)
+        c2 = c2.resized(256, 256)
+        row = {"triangles": sc.num_triangles}
+        for accel in (("none", "lbvh") if sc.num_triangles <= 20000 else ("lbvh",)):
+            gs = GpuScene(sc, accel=accel)
+            row[f"ms_{accel}"] = time_frames(gs, c2, n=3 if accel == "none" else 5)
+            gs.close()
+        rows.append(row)
+        log(f"[shapes] {sc.num_triangles} tris: " + ", ".join(f"{k} {v:.3f}" for k, v in row.items() if k != "triangles"))
+    res["triangles"] = rows
+    # (3) lights: 1..4 on the 3.4M-triangle scene at 1080p
+    big, bcam = sg.make_terrain_3m()
+    rows = []
+    for L in (1, 2, 3, 4):
+        gs = GpuScene(big.with_lights(big.lights[:L]))
+        rows.append({"lights": L, "ms": time_frames(gs, bcam)})
+        gs.close()
+        log(f"[shapes] {L} lights: {rows[-1]['ms']:.3f} ms")
+    res["lights"] = rows
+    # (4) launch configuration ("network size"): traversal workgroups per CU
+    gs = GpuScene(big)
+    saved = rt.rt_get_tuning()
+    rows = []
+    for per_cu in (1, 2, 3, 4, 5, 6):
+        rt.rt_set_tuning(per_cu, saved["stream_blocks"], saved["max_pass_paths"])
+        t = Timer()
+        ws = Workspace.for_camera(bcam, gs.num_lights)
+        out = alloc_outputs(bcam, gs.num_lights, torch.device("cuda:0"))
+        render_stereo(gs, bcam, workspace=ws, outputs=out)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            render_stereo(gs, bcam, workspace=ws, outputs=out, timer=t.handle)
+        st = t.read()
+        rows.append({"blocks_per_cu": per_cu, "trace_ms": st["trace"][0] / 3, "frame_ms": sum(v[0] for v in st.values()) / 3})
+        t.close()
+        log(f"[shapes] {per_cu} blocks/CU: trace {rows[-1]['trace_ms']:.3f} ms")
+    rt.rt_set_tuning(**saved)
+    res["launch_config"] = rows
+    # (5) stage split of one frame (Fig. 7): computation, transfer, other; sequential and overlapped readback
+    ws = Workspace.for_camera(bcam, gs.num_lights)
+    out = alloc_outputs(bcam, gs.num_lights, torch.device("cuda:0"), host=True)
+    t = Timer()
+    render_stereo(gs, bcam, workspace=ws, outputs=out)
+    torch.cuda.synchronize()
+    n = 5
+    t0 = time.perf_counter()
+    for _ in range(n):
+        render_stereo(gs, bcam, workspace=ws, outputs=out, timer=t.handle)  # readback on the same stream
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / n
+    st = t.read()
+    comp = sum(st[k][0] for k in ("trace", "shade", "resolve")) / n
+    xfer = st["readback"][0] / n
+    res["stage_split"] = {"frame_ms_wall": wall, "compute_ms": comp, "transfer_ms": xfer,
+                          "other_ms": max(0.0, wall - comp - xfer), "compute_share": comp / wall,
+                          "transfer_share": xfer / wall}
+    log(f"[shapes] stage split (sequential readback): compute {comp:.3f} ms, transfer {xfer:.3f} ms, wall {wall:.3f} ms")
+    t.close()
+    gs.close()
+    print(json.dumps({"metric": "paper experiment shapes", "config": {"workload": "paper_shapes"}, **res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +365,8 @@ def main():
         return
 
     rt.lib()
+    if args.workload == "paper_shapes":
+        return bench_paper_shapes(args)
     if args.workload == "serve":
         return bench_serve(args)
     if args.workload == "batch64":

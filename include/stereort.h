@@ -271,6 +271,28 @@ rt_status rt_autotune_batch(const rt_batch_item* items, int32_t n, void* workspa
                             uint32_t flags, void* stream, int32_t repeats, rt_tuning* best, double* best_ms);
 
 /* ---------------------------------------------------------------------------------------------
+ * Stereo-pair building (the paper's post-processing of the two channels, Section 3, Fig. 2)
+ * ------------------------------------------------------------------------------------------- */
+
+enum {
+  RT_COMPOSE_ANAGLYPH_RED_CYAN = 0, /* W x H: red from the left eye, green and blue from the right */
+  RT_COMPOSE_SIDE_BY_SIDE = 1       /* 2W x H: left eye's image, then the right eye's */
+};
+
+/* Builds an 8-bit RGBA display image from the two eyes' linear radiance
+ * ([H][W][3] FP32 each, device) into `out` (device, 4 bytes per output pixel,
+ * RGBA in memory order).  Each channel is encoded as
+ * floor(255 * sqrt(clamp(x * exposure, 0, 1)) + 0.5) with correctly rounded
+ * FP32 operations; alpha is 255.  Asynchronous on `stream`. */
+rt_status rt_compose_stereo(const float* left, const float* right, int32_t width, int32_t height, int32_t mode,
+                            float exposure, uint8_t* out, void* stream);
+
+/* Copies `bytes` (a multiple of 4) of device memory into pinned host memory
+ * with the narrow readback kernel (hipMemcpyAsync when `host` has no device
+ * view).  Asynchronous on `stream`. */
+rt_status rt_copy_to_host(const void* device, void* host, size_t bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Per-kernel timing (the paper's per-stage time accounting, Section 4)
  * ------------------------------------------------------------------------------------------- */
 

@@ -210,6 +210,36 @@ def intersect_plane(O, d, n, dist, tmin=0.0, tmax=np.inf):
     return bool(hit), float(t[0])
 
 
+def encode8(x, exposure=1.0):
+    """Display code of linear values: floor(255 * sqrt(clamp(x * exposure, 0, 1)) + 0.5), each step one
+    correctly rounded float32 operation (the same precision as the device path, which decides the same
+    integers)."""
+    x = np.asarray(x, np.float32)
+    v = np.float32(x * np.float32(exposure))
+    v = np.minimum(np.maximum(v, np.float32(0.0)), np.float32(1.0))
+    g = np.sqrt(v, dtype=np.float32)
+    m = np.float32(np.float32(255.0) * g)
+    return np.floor(np.float32(m + np.float32(0.5))).astype(np.uint8)
+
+
+def compose_stereo(left, right, mode="anaglyph", exposure=1.0):
+    """Stereo-pair building for a display (the paper's post-processing, Section 3, Fig. 2): a red-cyan
+    anaglyph (red from the left eye, green and blue from the right) or the two images side by side,
+    as 8-bit RGBA with alpha 255.  left/right: [H, W, 3] linear radiance."""
+    left = np.asarray(left, np.float32)
+    right = np.asarray(right, np.float32)
+    H, W, _ = left.shape
+    if mode == "anaglyph":
+        rgb = np.stack([encode8(left[..., 0], exposure), encode8(right[..., 1], exposure),
+                        encode8(right[..., 2], exposure)], axis=-1)
+    elif mode == "side_by_side":
+        rgb = np.concatenate([encode8(left, exposure), encode8(right, exposure)], axis=1)
+    else:
+        raise ValueError(mode)
+    alpha = np.full(rgb.shape[:2] + (1,), 255, np.uint8)
+    return np.concatenate([rgb, alpha], axis=-1)
+
+
 def closest_hits(scene, O, d, tmin=0.0, exclude=None):
     """Closest hit (t, prim id, margin) of explicit rays [n,3] against every primitive of the scene."""
     held = _Held()

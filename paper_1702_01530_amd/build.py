@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstereort.so")
-SOURCES = ["api.hip", "lbvh.hip", "render.hip"]
+SOURCES = ["api.hip", "lbvh.hip", "render.hip", "compose.hip"]
 ARCH = os.environ.get("STEREORT_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

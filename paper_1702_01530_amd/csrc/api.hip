@@ -726,6 +726,35 @@ rt_status rt_autotune_batch(const rt_batch_item* items, int32_t n, void* workspa
   return ok();
 }
 
+rt_status rt_compose_stereo(const float* left, const float* right, int32_t width, int32_t height, int32_t mode,
+                            float exposure, uint8_t* out, void* stream) {
+  if (!left || !right || !out) return fail(RT_ERR_INVALID_ARGUMENT, "compose needs left, right and out");
+  if (width < 1 || height < 1 || int64_t(width) * height > RT_MAX_PIXELS)
+    return fail(RT_ERR_INVALID_ARGUMENT, "image size %dx%d out of range", width, height);
+  if (mode != RT_COMPOSE_ANAGLYPH_RED_CYAN && mode != RT_COMPOSE_SIDE_BY_SIDE)
+    return fail(RT_ERR_INVALID_ARGUMENT, "unknown compose mode %d", mode);
+  if (!std::isfinite(exposure) || !(exposure > 0.f))
+    return fail(RT_ERR_INVALID_ARGUMENT, "exposure must be finite and > 0");
+  if (reinterpret_cast<uintptr_t>(out) & 3u) return fail(RT_ERR_INVALID_ARGUMENT, "out must be 4-byte aligned");
+  hipError_t e = srt::compose_stereo(left, right, width, height, mode, exposure, out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "compose launch");
+  return ok();
+}
+
+rt_status rt_copy_to_host(const void* device, void* host, size_t bytes, void* stream) {
+  if (!device || !host || bytes % 4 != 0) return fail(RT_ERR_INVALID_ARGUMENT, "bad copy arguments");
+  void* view = nullptr;
+  hipError_t e;
+  if (hipHostGetDevicePointer(&view, host, 0) == hipSuccess && view) {
+    e = srt::copy_to_host(device, view, bytes, kReadbackBlocks, static_cast<hipStream_t>(stream));
+  } else {
+    (void)hipGetLastError();
+    e = hipMemcpyAsync(host, device, bytes, hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream));
+  }
+  if (e != hipSuccess) return hip_fail(e, "copy to host");
+  return ok();
+}
+
 rt_status rt_timer_create(rt_timer* out) {
   if (!out) return fail(RT_ERR_INVALID_ARGUMENT, "timer pointer is NULL");
   *out = new (std::nothrow) rt_timer_s();

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 
@@ -173,6 +174,8 @@ struct RenderArgs {
 hipError_t upload_items(const DevItem* items, int n, DevItem* dst, hipStream_t stream);
 
 hipError_t render_chunk(const RenderArgs& a, hipStream_t stream, TimerImpl* timer);
+hipError_t compose_stereo(const float* left, const float* right, int W, int H, int mode, float exposure,
+                          uint8_t* out, hipStream_t s);
 // Copies `bytes` (a multiple of 4) from device memory into pinned host memory through its device view.
 hipError_t copy_to_host(const void* src, void* host_dst_device_view, size_t bytes, int blocks, hipStream_t s);
 

@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "RT_OK", 1: "RT_ERR_INVALID_ARGUMENT", 2: "RT_ERR_BUFFER_TOO_
 RT_ACCEL_LBVH, RT_ACCEL_NONE = 0, 1
 RT_FLAG_PATH_IDS, RT_FLAG_COUNT_WORK, RT_FLAG_BRUTE_FORCE, RT_FLAG_READBACK_MEMCPY = 1, 2, 4, 8
 RT_MAX_LIGHTS, RT_MAX_DEPTH = 8, 8
+RT_COMPOSE_ANAGLYPH_RED_CYAN, RT_COMPOSE_SIDE_BY_SIDE = 0, 1
 RT_NUM_COUNTERS = 8
 COUNTER_NAMES = ["primary", "reflection", "shadow", "closest_nodes", "closest_tris", "any_nodes", "any_tris", "errors"]
 RT_NUM_STAGES = 8
@@ -116,6 +117,9 @@ _SIGNATURES = {
     "rt_set_tuning": (C.c_int, [C.POINTER(rt_tuning)]),
     "rt_autotune_batch": (C.c_int, [C.POINTER(rt_batch_item), C.c_int32, C.c_void_p, C.c_size_t, C.c_uint32,
                                     C.c_void_p, C.c_int32, C.POINTER(rt_tuning), C.POINTER(C.c_double)]),
+    "rt_compose_stereo": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_void_p,
+                                    C.c_void_p]),
+    "rt_copy_to_host": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "rt_timer_create": (C.c_int, [C.POINTER(C.c_void_p)]),
     "rt_timer_destroy": (C.c_int, [C.c_void_p]),
     "rt_timer_read": (C.c_int, [C.c_void_p, C.POINTER(rt_timing)]),
@@ -239,6 +243,14 @@ def rt_autotune_batch(items, ws_ptr, ws_bytes, flags, stream, repeats=2):
     check(lib().rt_autotune_batch(items, len(items), ws_ptr, ws_bytes, flags, stream, repeats, C.byref(t),
                                   C.byref(ms)))
     return {k: getattr(t, k) for k, _ in rt_tuning._fields_}, ms.value
+
+
+def rt_compose_stereo(left_ptr, right_ptr, width, height, mode, exposure, out_ptr, stream):
+    check(lib().rt_compose_stereo(left_ptr, right_ptr, width, height, mode, exposure, out_ptr, stream))
+
+
+def rt_copy_to_host(dev_ptr, host_ptr, nbytes, stream):
+    check(lib().rt_copy_to_host(dev_ptr, host_ptr, nbytes, stream))
 
 
 def rt_timer_create():

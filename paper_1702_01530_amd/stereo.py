@@ -217,6 +217,18 @@ def autotune_batch(pairs, outputs: list, workspace: Workspace, repeats=2, stream
     return rt.rt_autotune_batch(items, workspace.ptr, workspace.nbytes, 0, stream_handle(stream), repeats)
 
 
+def compose(out: dict, mode: str = "anaglyph", exposure: float = 1.0, stream=None) -> torch.Tensor:
+    """Builds the 8-bit RGBA display image of a rendered stereo pair on the device
+    ("anaglyph": red-cyan, H x W x 4; "side_by_side": H x 2W x 4)."""
+    m = {"anaglyph": rt.RT_COMPOSE_ANAGLYPH_RED_CYAN, "side_by_side": rt.RT_COMPOSE_SIDE_BY_SIDE}[mode]
+    rad = out["radiance"]
+    H, W = rad.shape[1], rad.shape[2]
+    img = torch.empty((H, W * (2 if m == rt.RT_COMPOSE_SIDE_BY_SIDE else 1), 4), dtype=torch.uint8, device=rad.device)
+    rt.rt_compose_stereo(rad[0].data_ptr(), rad[1].data_ptr(), W, H, m, float(exposure), img.data_ptr(),
+                         stream_handle(stream))
+    return img
+
+
 class Timer:
     def __init__(self):
         self.handle = rt.rt_timer_create()

@@ -79,6 +79,15 @@ def test_camera_validation_and_workspace():
         rt.rt_render_workspace_size(bad, 4)
 
 
+def test_compose_validation_without_device():
+    L = rt.lib()
+    assert L.rt_compose_stereo(None, None, 4, 4, 0, 1.0, None, None) == rt.RT_ERR_INVALID_ARGUMENT
+    assert L.rt_compose_stereo(8, 8, 4, 4, 7, 1.0, 8, None) == rt.RT_ERR_INVALID_ARGUMENT
+    assert "mode" in rt.last_error()
+    assert L.rt_compose_stereo(8, 8, 4, 4, 0, -1.0, 8, None) == rt.RT_ERR_INVALID_ARGUMENT
+    assert L.rt_copy_to_host(None, None, 4, None) == rt.RT_ERR_INVALID_ARGUMENT
+
+
 def test_tuning_validation():
     saved = rt.rt_get_tuning()
     assert saved["max_pass_paths"] >= 4096 and saved["stream_blocks"] >= 1

@@ -237,6 +237,24 @@ def test_served_results_equal_standalone_renders(torch_cuda):
         g.close()
 
 
+@pytest.mark.parametrize("mode", ["anaglyph", "side_by_side"])
+def test_compose_matches_oracle(torch_cuda, mode):
+    """Stereo-pair building on the device decides the same 8-bit codes as the oracle's definition."""
+    torch = torch_cuda
+    from paper_1702_01530_amd.stereo import GpuScene, compose, render_stereo
+    scene, cam = sg.make_spheres_scene()
+    cam = cam.resized(45, 31)
+    gs = GpuScene(scene)
+    out = render_stereo(gs, cam)
+    for exposure in (1.0, 0.7, 3.0):
+        img = compose(out, mode, exposure)
+        torch.cuda.synchronize()
+        rad = out["radiance"].cpu().numpy()
+        ref = oracle.compose_stereo(rad[0], rad[1], mode, exposure)
+        assert np.array_equal(img.cpu().numpy(), ref), (mode, exposure)
+    gs.close()
+
+
 def test_degenerate_scenes(torch_cuda):
     torch = torch_cuda
     bg = (0.25, 0.5, 0.75)

@@ -460,3 +460,34 @@ def test_paper5_fixture_matches_paper_counts():
     scene, _ = sg.make_paper5_scene()
     assert [list(x) for x in scene.info["solids"]] == g["objects"]
     assert scene.num_triangles == g["total_polygons"]
+
+
+# ---------------------------------------------------------------------------------------------
+# Stereo-pair building
+# ---------------------------------------------------------------------------------------------
+
+def test_display_encoding_closed_forms():
+    x = np.array([0.0, 1.0, 0.25, 4.0, -1.0, 1.0 / 255.0 ** 2, 0.5], np.float32)
+    codes = oracle.encode8(x)
+    assert codes[0] == 0 and codes[1] == 255 and codes[3] == 255 and codes[4] == 0
+    assert codes[2] == 128  # sqrt(0.25) = 0.5 -> 127.5 + 0.5 -> 128
+    assert codes[5] == 1  # sqrt(1/255^2) = 1/255 -> 1.5 -> 1
+    assert codes[6] == 180  # 255 * 0.70710677 = 180.31 -> 180
+    assert oracle.encode8(np.float32(0.25), exposure=4.0) == 255
+    # monotone and onto 0..255 over [0, 1]
+    ramp = oracle.encode8(np.linspace(0, 1, 200001, dtype=np.float32))
+    assert np.all(np.diff(ramp.astype(int)) >= 0) and set(ramp) == set(range(256))
+
+
+def test_anaglyph_and_side_by_side_layout():
+    rng = np.random.default_rng(3)
+    L = rng.uniform(0, 1.2, (5, 7, 3)).astype(np.float32)
+    R = rng.uniform(0, 1.2, (5, 7, 3)).astype(np.float32)
+    a = oracle.compose_stereo(L, R, "anaglyph")
+    assert a.shape == (5, 7, 4) and np.all(a[..., 3] == 255)
+    assert np.array_equal(a[..., 0], oracle.encode8(L[..., 0]))
+    assert np.array_equal(a[..., 1], oracle.encode8(R[..., 1]))
+    assert np.array_equal(a[..., 2], oracle.encode8(R[..., 2]))
+    sbs = oracle.compose_stereo(L, R, "side_by_side")
+    assert sbs.shape == (5, 14, 4)
+    assert np.array_equal(sbs[:, :7, :3], oracle.encode8(L)) and np.array_equal(sbs[:, 7:, :3], oracle.encode8(R))
