@@ -24,7 +24,9 @@ METRIC = "Mrays/s and stereo frames/s (1080p, 2M tris) at 1 GPU; p50/p99 latency
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes (what the traversal must read and write if nothing were cached).
-NODE_BYTES = 64      # one BVH2 node visit
+# A node visit reads the node's child boxes and child references: 64 B of a 64 B two-wide node,
+# 112 B (six 16 B box planes + 16 B of references) of a 128 B four-wide node.
+NODE_VISIT_BYTES = {64: 64, 128: 112}  # node record size -> bytes one visit reads
 TRI_BYTES = 48       # one triangle record test
 CLOSEST_RAY_IO = 32 + 8   # ray in (origin+path, direction+exclude) + hit out (t, key)
 ANY_RAY_IO = 32 + 1       # shadow record in + visibility byte out
@@ -394,8 +396,9 @@ def main():
         raise SystemExit("internal consistency check fired during the counting pass")
     rays = int(cnt[0] + cnt[1] + cnt[2])
     closest_rays, any_rays = int(cnt[0] + cnt[1]), int(cnt[2])
-    closest_bytes = NODE_BYTES * cnt[3] + TRI_BYTES * cnt[4] + CLOSEST_RAY_IO * closest_rays
-    any_bytes = NODE_BYTES * cnt[5] + TRI_BYTES * cnt[6] + ANY_RAY_IO * any_rays
+    node_visit = NODE_VISIT_BYTES[info["node_bytes"] // max(info["num_nodes"], 1)]
+    closest_bytes = node_visit * cnt[3] + TRI_BYTES * cnt[4] + CLOSEST_RAY_IO * closest_rays
+    any_bytes = node_visit * cnt[5] + TRI_BYTES * cnt[6] + ANY_RAY_IO * any_rays
     log(f"[bench] rays/frame {rays} (primary {cnt[0]}, mirror {cnt[1]}, shadow {cnt[2]}); "
         f"closest: {cnt[3] / max(closest_rays, 1):.1f} nodes + {cnt[4] / max(closest_rays, 1):.1f} tris per ray; "
         f"shadow: {cnt[5] / max(any_rays, 1):.1f} nodes + {cnt[6] / max(any_rays, 1):.1f} tris per ray")
@@ -486,7 +489,7 @@ def main():
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(args.workload),
             "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms,
-            "launches_per_frame": launches_per_frame,
+            "launches_per_frame": launches_per_frame, "node_visit_bytes": node_visit,
             "bytes_per_frame": {"closest": int(closest_bytes), "shadow": int(any_bytes)},
         },
     }

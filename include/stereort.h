@@ -137,7 +137,7 @@ typedef struct {
   int64_t num_triangles, num_spheres, num_planes, num_lights, num_materials;
   int32_t bvh_depth;     /* levels from the root to the deepest leaf (0 without a BVH) */
   int32_t leaf_size;     /* largest number of triangles per leaf */
-  int64_t num_nodes;     /* BVH2 nodes, 64 bytes each */
+  int64_t num_nodes;     /* BVH nodes (node_bytes / num_nodes bytes each) */
   int64_t node_bytes, triangle_bytes;
   float bounds_lo[3], bounds_hi[3];
 } rt_scene_info;
