@@ -234,6 +234,23 @@ struct Stack {
     lds[(sp & (kStackLds - 1)) * kBlock] = uint32_t(v);
     ++sp;
   }
+  // Pushes the np (1..3) entries c3, c2, c1 of which the last np are live (c1 ends on top).  With
+  // room for three entries below the LDS ring's wrap point all three slots are written
+  // unconditionally (entries above the new top are dead), so the common case takes no branch.
+  __device__ inline void push_sorted(int c1, int c2, int c3, int np) {
+    if (sp + 3 <= kStackLds) {
+      const int s0 = np == 1 ? c1 : (np == 2 ? c2 : c3);
+      const int s1 = np == 2 ? c1 : c2;
+      lds[sp * kBlock] = uint32_t(s0);
+      lds[(sp + 1) * kBlock] = uint32_t(s1);
+      lds[(sp + 2) * kBlock] = uint32_t(c1);
+      sp += np;
+    } else {
+      if (np >= 3) push(c3);
+      if (np >= 2) push(c2);
+      push(c1);
+    }
+  }
   __device__ inline int pop() {
     --sp;
     int v = int(lds[(sp & (kStackLds - 1)) * kBlock]);
@@ -241,6 +258,27 @@ struct Stack {
     return v;
   }
 };
+
+// Orders four (entry distance, child) pairs by distance; missed children (at +inf) sort last.
+__device__ __attribute__((always_inline)) inline void sort4(float (&t)[4], int (&r)[4]) {
+  auto cas = [&](int i, int j) {
+    const bool sw = t[j] < t[i];
+    const float ti = t[i], tj = t[j];
+    const int ri = r[i], rj = r[j];
+    t[i] = sw ? tj : ti;
+    t[j] = sw ? ti : tj;
+    r[i] = sw ? rj : ri;
+    r[j] = sw ? ri : rj;
+  };
+  cas(0, 1);
+  cas(2, 3);
+  cas(0, 2);
+  cas(1, 3);
+  cas(1, 2);
+}
+
+// Value of the `node` register once a ray's traversal is finished (never a node index).
+constexpr int kDoneRef = 0x7fffffff;
 
 struct Best {
   float t;
@@ -292,6 +330,56 @@ __device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tm
   }
   const float3 inv = make_float3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
   const float3 oi = mul(o, inv);
+#if SRT_BVH_WIDTH == 4
+  // Each iteration takes one internal-node step and then, if the lane now holds a leaf, tests it,
+  // so the leaf step of a wave runs with every lane that reached a leaf in this iteration.
+  int node = sc.root;
+  st.sp = 0;
+  // A valid tree visits each node and leaf at most once; the cap only guards against a corrupt one.
+  for (int64_t guard = 2 * int64_t(sc.T) + 64; guard > 0; --guard) {
+    if (node >= 0) {
+      if (node >= sc.num_nodes) {  // corrupt reference: stop this ray, never read out of bounds
+        st.overflow = true;
+        return;
+      }
+      if (COUNT) ++nnodes;
+      const float tmax = limit();
+      const float4* n = sc.nodes + 8 * node;
+      const float4 lx = n[0], hx = n[1], ly = n[2], hy = n[3], lz = n[4], hz = n[5], cr = n[6];
+      float t[4] = {slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, inv, oi, tmin, tmax),
+                    slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, inv, oi, tmin, tmax),
+                    slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, inv, oi, tmin, tmax),
+                    slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, inv, oi, tmin, tmax)};
+      int r[4] = {__float_as_int(cr.x), __float_as_int(cr.y), __float_as_int(cr.z), __float_as_int(cr.w)};
+      sort4(t, r);
+      if (t[0] < INFINITY) {
+        node = r[0];
+        const int np = int(t[1] < INFINITY) + int(t[2] < INFINITY) + int(t[3] < INFINITY);
+        if (np > 0) st.push_sorted(r[1], r[2], r[3], np);
+      } else {
+        node = st.sp > 0 ? st.pop() : kDoneRef;
+      }
+    }
+    if (node < 0) {
+      const int code = ~node;
+      const int first = code >> 2, count = (code & 3) + 1;
+      if (first + count > sc.T) {
+        st.overflow = true;
+        return;
+      }
+      for (int k = 0; k < count; ++k) {
+        const int r = first + k;
+        int id;
+        const float t = tri_t(sc.tris, r, o, d, tmin, limit(), &id);
+        if (COUNT) ++ntris;
+        if (accept(t, r, id)) return;
+      }
+      node = st.sp > 0 ? st.pop() : kDoneRef;
+    }
+    if (node == kDoneRef) return;
+  }
+  st.overflow = true;
+#else
   int node = sc.root;
   st.sp = 0;
   // A valid tree visits each node at most once; the cap only guards against a corrupt one.
@@ -303,7 +391,6 @@ __device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tm
       }
       if (COUNT) ++nnodes;
       const float tmax = limit();
-#if SRT_BVH_WIDTH == 2
       const float4* n = sc.nodes + 4 * node;
       const float4 a = n[0], b = n[1], c = n[2], e = n[3];
       const float t0 = slab(a.x, a.y, a.z, a.w, c.x, c.y, inv, oi, tmin, tmax);
@@ -324,37 +411,6 @@ __device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tm
         node = c1;
         continue;
       }
-#else
-      const float4* n = sc.nodes + 8 * node;
-      const float4 lx = n[0], hx = n[1], ly = n[2], hy = n[3], lz = n[4], hz = n[5], cr = n[6];
-      float t[4] = {slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, inv, oi, tmin, tmax),
-                    slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, inv, oi, tmin, tmax),
-                    slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, inv, oi, tmin, tmax),
-                    slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, inv, oi, tmin, tmax)};
-      int r[4] = {__float_as_int(cr.x), __float_as_int(cr.y), __float_as_int(cr.z), __float_as_int(cr.w)};
-      // order the four children by entry distance (missed ones, at +inf, sort last)
-      auto cas = [&](int i, int j) {
-        const bool sw = t[j] < t[i];
-        const float ti = t[i], tj = t[j];
-        const int ri = r[i], rj = r[j];
-        t[i] = sw ? tj : ti;
-        t[j] = sw ? ti : tj;
-        r[i] = sw ? rj : ri;
-        r[j] = sw ? ri : rj;
-      };
-      cas(0, 1);
-      cas(2, 3);
-      cas(0, 2);
-      cas(1, 3);
-      cas(1, 2);
-      if (t[0] < INFINITY) {
-        if (t[3] < INFINITY) st.push(r[3]);
-        if (t[2] < INFINITY) st.push(r[2]);
-        if (t[1] < INFINITY) st.push(r[1]);
-        node = r[0];
-        continue;
-      }
-#endif
     } else {
       const int code = ~node;
       const int first = code >> 2, count = (code & 3) + 1;
@@ -374,6 +430,7 @@ __device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tm
     node = st.pop();
   }
   st.overflow = true;
+#endif
 }
 
 __device__ inline void add_work(Counters* ctr, int slot, uint32_t v) {
