@@ -24,9 +24,10 @@ METRIC = "Mrays/s and stereo frames/s (1080p, 2M tris) at 1 GPU; p50/p99 latency
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes (what the traversal must read and write if nothing were cached).
-# A node visit reads the node's child boxes and child references: 64 B of a 64 B two-wide node,
-# 112 B (six 16 B box planes + 16 B of references) of a 128 B four-wide node.
-NODE_VISIT_BYTES = {64: 64, 128: 112}  # node record size -> bytes one visit reads
+# A node visit reads the node's child boxes and child references: 56 B of a 64 B four-wide node with
+# quantised boxes (corner + exponents 16 B, references 16 B, 24 B of 8-bit grid coordinates), 112 B
+# of a 128 B four-wide node with FP32 boxes (six 16 B box planes + 16 B of references).
+NODE_VISIT_BYTES = {64: 56, 128: 112}  # node record size -> bytes one visit reads
 TRI_BYTES = 48       # one triangle record test
 CLOSEST_RAY_IO = 32 + 8   # ray in (origin+path, direction+exclude) + hit out (t, key)
 ANY_RAY_IO = 32 + 1       # shadow record in + visibility byte out

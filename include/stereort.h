@@ -120,7 +120,8 @@ rt_status rt_scene_storage_size(const rt_scene_desc* desc, size_t* storage_bytes
 
 /* Builds the scene into caller-owned device memory and returns a host handle.
  * Validates the descriptor on the host and the device arrays on the device
- * (finite coordinates, positive radii, material indices in range); a bad
+ * (finite coordinates, triangle vertices within +-RT_MAX_COORD, positive radii,
+ * material indices in range); a bad
  * array gives RT_ERR_INVALID_ARGUMENT.  Copies materials and lights from host
  * memory.  BLOCKS until the build has finished on `stream` (it reads back the
  * validation result).  The input arrays and the scratch may be reused or freed
@@ -160,6 +161,7 @@ typedef struct {
 } rt_stereo_camera;
 
 #define RT_MAX_DEPTH 8
+#define RT_MAX_COORD 1e18f /* largest |coordinate| of a triangle vertex */
 #define RT_MAX_PIXELS ((int64_t)1 << 28) /* width * height per eye */
 
 enum {

@@ -460,7 +460,8 @@ rt_status rt_scene_build(const rt_scene_desc* desc, void* storage, size_t storag
   char* st = static_cast<char*>(storage);
   e = srt::build_scene_device(desc, plan, st, static_cast<char*>(scratch), static_cast<hipStream_t>(stream), &res);
   if (e != hipSuccess) return hip_fail(e, "scene build");
-  if (res.status_bits & 1u) return fail(RT_ERR_INVALID_ARGUMENT, "a triangle vertex is not finite");
+  if (res.status_bits & 1u)
+    return fail(RT_ERR_INVALID_ARGUMENT, "a triangle vertex is not finite or exceeds %g in magnitude", RT_MAX_COORD);
   if (res.status_bits & 2u) return fail(RT_ERR_INVALID_ARGUMENT, "a triangle material index is out of range");
   if (res.status_bits & 4u)
     return fail(RT_ERR_INVALID_ARGUMENT, "a sphere is not finite, has radius <= 0 or a material out of range");

@@ -6,12 +6,13 @@
 //   2. reduction of the centroid and scene bounds;
 //   3. 63-bit Morton code of the centroid quantised to 2^21 cells per axis;
 //   4. stable LSD radix sort of (code, triangle id), 8 passes of 8 bits;
-//   5. Karras (2012) emission of the T-1 internal nodes from the sorted codes
-//      (split at the highest differing bit; equal codes split by index);
+//   5. Karras (2012) emission of the T-1 internal nodes of a binary tree from the
+//      sorted codes (split at the highest differing bit; equal codes split by index);
 //   6. bottom-up box refit (an atomic arrival counter per node, the second
 //      child to arrive unions both boxes and climbs on);
-//   7. packing into 64-byte BVH2 nodes that carry both children's boxes, and
-//      48-byte triangle records in leaf order.
+//   7. top-down collapse into a 4-wide tree, one level per launch, with the
+//      children's boxes quantised to 8 bits on each node's own grid (64-byte
+//      nodes), and 48-byte triangle records in leaf order.
 // No SAH.  Every step is deterministic, so a scene always builds the same tree.
 
 #include <hip/hip_runtime.h>
@@ -23,13 +24,10 @@
 
 #include "rt_internal.h"
 
-#ifndef SRT_LEAF_SIZE
-#define SRT_LEAF_SIZE 1
-#endif
 
 namespace srt {
 
-int leaf_size() { return SRT_LEAF_SIZE; }
+int leaf_size() { return 1; }  // every leaf of the collapsed tree is one triangle
 
 namespace {
 
@@ -67,7 +65,9 @@ __global__ __launch_bounds__(kBlock) void k_tri_prep(const float* __restrict__ t
     float v[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) v[k] = p[k];
-    bool ok = finite3(v[0], v[1], v[2]) && finite3(v[3], v[4], v[5]) && finite3(v[6], v[7], v[8]);
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) ok = ok && fabsf(v[k]) <= RT_MAX_COORD;  // false for NaN and inf too
     if (!ok) atomicOr(status, 1u);
     if (mat[i] >= uint32_t(M)) atomicOr(status, 2u);
 #pragma unroll
@@ -404,59 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_refit(const int2* __restrict__ child
 }
 
 // ---------------------------------------------------------------------------------------------
-// 7. Packing
-// ---------------------------------------------------------------------------------------------
-
-struct PackArgs {
-  const int2* children;
-  const int2* range;
-  const float4* leaf_lo;
-  const float4* leaf_hi;
-  const uint32_t* sorted_ids;
-  const float4* nodebox;
-  float4* nodes;
-  int64_t n;
-  float pad;
-  int leaf_size;
-};
-
-__device__ inline void child_box(const PackArgs& a, int ref, float4* lo, float4* hi) {
-  if (ref < 0) {
-    uint32_t id = a.sorted_ids[~ref];
-    *lo = a.leaf_lo[id];
-    *hi = a.leaf_hi[id];
-  } else {
-    *lo = a.nodebox[2 * ref];
-    *hi = a.nodebox[2 * ref + 1];
-  }
-}
-
-// Reference to emit for a Karras child: subtrees of at most leaf_size triangles become one leaf.
-__device__ inline int child_ref(const PackArgs& a, int ref) {
-  if (ref < 0) return ~((~ref) << 2);
-  int2 r = a.range[ref];
-  int count = r.y - r.x + 1;
-  if (count <= a.leaf_size) return ~((r.x << 2) | (count - 1));
-  return ref;
-}
-
-__global__ __launch_bounds__(kBlock) void k_pack_nodes(PackArgs a) {
-  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= a.n - 1) return;
-  int2 ch = a.children[i];
-  float4 l0, h0, l1, h1;
-  child_box(a, ch.x, &l0, &h0);
-  child_box(a, ch.y, &l1, &h1);
-  const float p = a.pad;
-  float4* out = a.nodes + 4 * i;
-  out[0] = make_float4(l0.x - p, h0.x + p, l0.y - p, h0.y + p);
-  out[1] = make_float4(l1.x - p, h1.x + p, l1.y - p, h1.y + p);
-  out[2] = make_float4(l0.z - p, h0.z + p, l1.z - p, h1.z + p);
-  out[3] = make_float4(__int_as_float(child_ref(a, ch.x)), __int_as_float(child_ref(a, ch.y)), 0.f, 0.f);
-}
-
-// ---------------------------------------------------------------------------------------------
-// 7b. Collapse into a 4-wide BVH, top-down one level at a time.  A BVH4 node takes a BVH2 node's two
+// 7. Collapse into a 4-wide BVH, top-down one level at a time.  A BVH4 node takes a binary node's two
 // children and, while it has fewer than four, replaces its largest-area internal child by that
 // child's two children (keeping left-to-right order).  Internal children become the next level's
 // nodes; their indices come from a prefix sum, so the layout is deterministic and each level's
@@ -471,9 +419,9 @@ struct WideArgs {
   const float4* leaf_lo;
   const float4* leaf_hi;
   const uint32_t* sorted_ids;
-  const int2* frontier;  // (BVH2 node, BVH4 index)
+  const int2* frontier;  // (binary node, BVH4 index)
   int64_t m;
-  int4* sel;             // chosen BVH2 references per frontier item
+  int4* sel;             // chosen binary-tree references per frontier item
   uint32_t* nint;        // internal children per item -> exclusive offsets (+ total at [m])
   int2* next;            // next frontier
   float4* nodes;         // 8 float4 per BVH4 node
@@ -564,6 +512,55 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(WideArgs a) {
     lo[0][k] = l.x, lo[1][k] = l.y, lo[2][k] = l.z;
     hi[0][k] = h.x, hi[1][k] = h.y, hi[2][k] = h.z;
   }
+#if SRT_QNODE
+  // Quantise the children's boxes on the node's own grid: per axis a power-of-two step s with
+  // 255 s >= the node's extent, lower corners rounded down and upper corners rounded up.  The
+  // differences are formed in FP64 and nudged outwards by one FP64 ulp, so the exact grid box always
+  // contains the padded FP32 box.
+  float plo[3], phi[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    plo[ax] = INFINITY;
+    phi[ax] = -INFINITY;
+    for (int k = 0; k < 4; ++k)
+      if (r[k] != kWideEmpty) {
+        plo[ax] = fminf(plo[ax], lo[ax][k]);
+        phi[ax] = fmaxf(phi[ax], hi[ax][k]);
+      }
+  }
+  uint32_t qlo[3] = {0u, 0u, 0u}, qhi[3] = {0u, 0u, 0u}, ebits = 0u;
+  for (int ax = 0; ax < 3; ++ax) {
+    const double base = double(plo[ax]);
+    const double ext = nextafter(double(phi[ax]) - base, INFINITY);
+    int e = -126;
+    if (ext > 0.0) {
+      int k2;
+      frexp(ext / 255.0, &k2);
+      e = k2;
+      while (e > -126 && ldexp(255.0, e - 1) >= ext) --e;
+      while (ldexp(255.0, e) < ext) ++e;
+    }
+    const double step = ldexp(1.0, e);
+    ebits |= uint32_t(e + 127) << (8 * ax);
+    for (int k = 0; k < 4; ++k) {
+      uint32_t ql = 255u, qh = 0u;
+      if (r[k] != kWideEmpty) {
+        const double dl = nextafter(double(lo[ax][k]) - base, -INFINITY);
+        const double dh = nextafter(double(hi[ax][k]) - base, INFINITY);
+        ql = uint32_t(fmin(fmax(floor(dl / step), 0.0), 255.0));
+        qh = uint32_t(fmin(fmax(ceil(dh / step), 0.0), 255.0));
+      }
+      qlo[ax] |= ql << (8 * k);
+      qhi[ax] |= qh << (8 * k);
+    }
+  }
+  for (int k = 1; k < 4; ++k)
+    if (r[k] == kWideEmpty) ref[k] = ref[0];
+  float4* out = a.nodes + 4 * int64_t(b4);
+  out[0] = make_float4(plo[0], plo[1], plo[2], __uint_as_float(ebits));
+  out[1] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), __int_as_float(ref[2]), __int_as_float(ref[3]));
+  out[2] = make_float4(__uint_as_float(qlo[0]), __uint_as_float(qhi[0]), __uint_as_float(qlo[1]), __uint_as_float(qhi[1]));
+  out[3] = make_float4(__uint_as_float(qlo[2]), __uint_as_float(qhi[2]), 0.f, 0.f);
+#else
   float4* out = a.nodes + 8 * int64_t(b4);
   out[0] = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
   out[1] = make_float4(hi[0][0], hi[0][1], hi[0][2], hi[0][3]);
@@ -573,6 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(WideArgs a) {
   out[5] = make_float4(hi[2][0], hi[2][1], hi[2][2], hi[2][3]);
   out[6] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), __int_as_float(ref[2]), __int_as_float(ref[3]));
   out[7] = make_float4(0.f, 0.f, 0.f, 0.f);
+#endif
 }
 
 __global__ void k_set_int2(int2* p, int2 v) { *p = v; }
@@ -767,62 +765,46 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
       SRT_CHECK(hipMemcpyAsync(&bounds, partial, sizeof(bounds), hipMemcpyDeviceToHost, stream));
       SRT_CHECK(hipMemcpyAsync(&depth, dmax, sizeof(depth), hipMemcpyDeviceToHost, stream));
       SRT_CHECK(hipStreamSynchronize(stream));
-      float m = 0.f;
-      for (int a = 0; a < 3; ++a) m = std::max(m, std::max(std::fabs(bounds.blo[a]), std::fabs(bounds.bhi[a])));
-      PackArgs pa;
-      pa.children = children;
-      pa.range = range;
-      pa.leaf_lo = lo;
-      pa.leaf_hi = hi;
-      pa.sorted_ids = i0;
-      pa.nodebox = nodebox;
-      pa.nodes = reinterpret_cast<float4*>(storage + plan.nodes_off);
-      pa.n = T;
-      pa.pad = m * 0x1p-18f + 1e-20f;  // conservative box growth (slab and triangle-test rounding)
-      pa.leaf_size = SRT_LEAF_SIZE;
-      if (kNodeWidth == 2) {
-        k_pack_nodes<<<blocks_for(T - 1), kBlock, 0, stream>>>(pa);
+      float coord_max = 0.f;
+      for (int a = 0; a < 3; ++a)
+        coord_max = std::max(coord_max, std::max(std::fabs(bounds.blo[a]), std::fabs(bounds.bhi[a])));
+      WideArgs wa;
+      wa.children = children;
+      wa.nodebox = nodebox;
+      wa.leaf_lo = lo;
+      wa.leaf_hi = hi;
+      wa.sorted_ids = i0;
+      wa.sel = reinterpret_cast<int4*>(scratch + plan.sel_off);
+      wa.nint = reinterpret_cast<uint32_t*>(scratch + plan.nint_off);
+      wa.nodes = reinterpret_cast<float4*>(storage + plan.nodes_off);
+      wa.pad = coord_max * 0x1p-18f + 1e-20f;  // conservative box growth (slab and triangle-test rounding)
+      int2* fr[2] = {reinterpret_cast<int2*>(scratch + plan.frontier_off[0]),
+                     reinterpret_cast<int2*>(scratch + plan.frontier_off[1])};
+      k_set_int2<<<1, 1, 0, stream>>>(fr[0], make_int2(0, 0));
+      SRT_LAUNCH_CHECK();
+      int64_t m = 1, allocated = 1;
+      int levels = 0;
+      while (m > 0) {
+        wa.frontier = fr[levels & 1];
+        wa.next = fr[(levels + 1) & 1];
+        wa.m = m;
+        wa.level_base = allocated;
+        k_wide_select<<<blocks_for(m), kBlock, 0, stream>>>(wa);
         SRT_LAUNCH_CHECK();
-        result->num_nodes = T - 1;
-      } else {
-        WideArgs wa;
-        wa.children = children;
-        wa.nodebox = nodebox;
-        wa.leaf_lo = lo;
-        wa.leaf_hi = hi;
-        wa.sorted_ids = i0;
-        wa.sel = reinterpret_cast<int4*>(scratch + plan.sel_off);
-        wa.nint = reinterpret_cast<uint32_t*>(scratch + plan.nint_off);
-        wa.nodes = pa.nodes;
-        wa.pad = pa.pad;
-        int2* fr[2] = {reinterpret_cast<int2*>(scratch + plan.frontier_off[0]),
-                       reinterpret_cast<int2*>(scratch + plan.frontier_off[1])};
-        k_set_int2<<<1, 1, 0, stream>>>(fr[0], make_int2(0, 0));
+        k_scan_exclusive<<<1, 1024, 0, stream>>>(wa.nint, m, wa.nint + m);
         SRT_LAUNCH_CHECK();
-        int64_t m = 1, allocated = 1;
-        int levels = 0;
-        while (m > 0) {
-          wa.frontier = fr[levels & 1];
-          wa.next = fr[(levels + 1) & 1];
-          wa.m = m;
-          wa.level_base = allocated;
-          k_wide_select<<<blocks_for(m), kBlock, 0, stream>>>(wa);
-          SRT_LAUNCH_CHECK();
-          k_scan_exclusive<<<1, 1024, 0, stream>>>(wa.nint, m, wa.nint + m);
-          SRT_LAUNCH_CHECK();
-          k_wide_emit<<<blocks_for(m), kBlock, 0, stream>>>(wa);
-          SRT_LAUNCH_CHECK();
-          uint32_t next_m = 0;
-          SRT_CHECK(hipMemcpyAsync(&next_m, wa.nint + m, sizeof(next_m), hipMemcpyDeviceToHost, stream));
-          SRT_CHECK(hipStreamSynchronize(stream));
-          allocated += next_m;
-          m = next_m;
-          ++levels;
-          if (levels > 128 || allocated > T - 1) return hipErrorUnknown;  // impossible for a valid hierarchy
-        }
-        result->num_nodes = allocated;
-        depth = levels;
+        k_wide_emit<<<blocks_for(m), kBlock, 0, stream>>>(wa);
+        SRT_LAUNCH_CHECK();
+        uint32_t next_m = 0;
+        SRT_CHECK(hipMemcpyAsync(&next_m, wa.nint + m, sizeof(next_m), hipMemcpyDeviceToHost, stream));
+        SRT_CHECK(hipStreamSynchronize(stream));
+        allocated += next_m;
+        m = next_m;
+        ++levels;
+        if (levels > 128 || allocated > T - 1) return hipErrorUnknown;  // impossible for a valid hierarchy
       }
+      result->num_nodes = allocated;
+      depth = levels;
       k_pack_tris<<<blocks_for(T), kBlock, 0, stream>>>(desc->triangles, desc->tri_material, i0, T, recs);
       SRT_LAUNCH_CHECK();
       result->root = 0;

@@ -211,6 +211,54 @@ __device__ inline float slab(float lox, float hix, float loy, float hiy, float l
   return tn <= tf ? tn : INFINITY;
 }
 
+// Entry distances of the four children of BVH4 node `node` (+inf where the ray misses the child's
+// box inside [tmin, tmax]) and their references.
+__device__ __attribute__((always_inline)) inline void node4_children(const float4* __restrict__ nodes, int node,
+                                                                     float3 inv, float3 oi, float tmin, float tmax,
+                                                                     float (&t)[4], int (&r)[4]) {
+#if SRT_QNODE
+  // Slab planes of child k on axis a are p_a + q s_a, i.e. t = q (s_a / d_a) + (p_a - o_a) / d_a; the
+  // near and far planes of an axis are picked once per node from the ray's direction sign.
+  const float4* n = nodes + 4 * node;
+  const float4 n0 = n[0], n1 = n[1], n2 = n[2];
+  const float2 n3 = reinterpret_cast<const float2*>(n)[6];
+  const uint32_t eb = __float_as_uint(n0.w);
+  const float ax = __uint_as_float((eb << 23) & 0x7f800000u) * inv.x;
+  const float ay = __uint_as_float((eb << 15) & 0x7f800000u) * inv.y;
+  const float az = __uint_as_float((eb << 7) & 0x7f800000u) * inv.z;
+  const float bx = fmaf(n0.x, inv.x, -oi.x), by = fmaf(n0.y, inv.y, -oi.y), bz = fmaf(n0.z, inv.z, -oi.z);
+  const bool px = inv.x >= 0.f, py = inv.y >= 0.f, pz = inv.z >= 0.f;
+  const uint32_t qlx = __float_as_uint(n2.x), qhx = __float_as_uint(n2.y), qly = __float_as_uint(n2.z),
+                 qhy = __float_as_uint(n2.w), qlz = __float_as_uint(n3.x), qhz = __float_as_uint(n3.y);
+  const uint32_t nx = px ? qlx : qhx, fx = px ? qhx : qlx, ny = py ? qly : qhy, fy = py ? qhy : qly,
+                 nz = pz ? qlz : qhz, fz = pz ? qhz : qlz;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float xn = fmaf(float((nx >> (8 * k)) & 0xffu), ax, bx), xf = fmaf(float((fx >> (8 * k)) & 0xffu), ax, bx);
+    const float yn = fmaf(float((ny >> (8 * k)) & 0xffu), ay, by), yf = fmaf(float((fy >> (8 * k)) & 0xffu), ay, by);
+    const float zn = fmaf(float((nz >> (8 * k)) & 0xffu), az, bz), zf = fmaf(float((fz >> (8 * k)) & 0xffu), az, bz);
+    const float tn = fmaxf(fmaxf(xn, yn), fmaxf(zn, tmin));
+    const float tf = fminf(fminf(xf, yf), fminf(zf, tmax));
+    t[k] = tn <= tf ? tn : INFINITY;
+  }
+  r[0] = __float_as_int(n1.x);
+  r[1] = __float_as_int(n1.y);
+  r[2] = __float_as_int(n1.z);
+  r[3] = __float_as_int(n1.w);
+#else
+  const float4* n = nodes + 8 * node;
+  const float4 lx = n[0], hx = n[1], ly = n[2], hy = n[3], lz = n[4], hz = n[5], cr = n[6];
+  t[0] = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, inv, oi, tmin, tmax);
+  t[1] = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, inv, oi, tmin, tmax);
+  t[2] = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, inv, oi, tmin, tmax);
+  t[3] = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, inv, oi, tmin, tmax);
+  r[0] = __float_as_int(cr.x);
+  r[1] = __float_as_int(cr.y);
+  r[2] = __float_as_int(cr.z);
+  r[3] = __float_as_int(cr.w);
+#endif
+}
+
 // ---------------------------------------------------------------------------------------------
 // Traversal stack: kStackLds entries per lane in LDS used as a ring; older entries spill to
 // a lane-interleaved area of the workspace.
@@ -330,7 +378,6 @@ __device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tm
   }
   const float3 inv = make_float3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
   const float3 oi = mul(o, inv);
-#if SRT_BVH_WIDTH == 4
   // Each iteration takes one internal-node step and then, if the lane now holds a leaf, tests it,
   // so the leaf step of a wave runs with every lane that reached a leaf in this iteration.
   int node = sc.root;
@@ -344,13 +391,9 @@ __device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tm
       }
       if (COUNT) ++nnodes;
       const float tmax = limit();
-      const float4* n = sc.nodes + 8 * node;
-      const float4 lx = n[0], hx = n[1], ly = n[2], hy = n[3], lz = n[4], hz = n[5], cr = n[6];
-      float t[4] = {slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, inv, oi, tmin, tmax),
-                    slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, inv, oi, tmin, tmax),
-                    slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, inv, oi, tmin, tmax),
-                    slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, inv, oi, tmin, tmax)};
-      int r[4] = {__float_as_int(cr.x), __float_as_int(cr.y), __float_as_int(cr.z), __float_as_int(cr.w)};
+      float t[4];
+      int r[4];
+      node4_children(sc.nodes, node, inv, oi, tmin, tmax, t, r);
       sort4(t, r);
       if (t[0] < INFINITY) {
         node = r[0];
@@ -379,58 +422,6 @@ __device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tm
     if (node == kDoneRef) return;
   }
   st.overflow = true;
-#else
-  int node = sc.root;
-  st.sp = 0;
-  // A valid tree visits each node at most once; the cap only guards against a corrupt one.
-  for (int64_t guard = 2 * int64_t(sc.T) + 64; guard > 0; --guard) {
-    if (node >= 0) {
-      if (node >= sc.num_nodes) {  // corrupt reference: stop this ray, never read out of bounds
-        st.overflow = true;
-        return;
-      }
-      if (COUNT) ++nnodes;
-      const float tmax = limit();
-      const float4* n = sc.nodes + 4 * node;
-      const float4 a = n[0], b = n[1], c = n[2], e = n[3];
-      const float t0 = slab(a.x, a.y, a.z, a.w, c.x, c.y, inv, oi, tmin, tmax);
-      const float t1 = slab(b.x, b.y, b.z, b.w, c.z, c.w, inv, oi, tmin, tmax);
-      const int c0 = __float_as_int(e.x), c1 = __float_as_int(e.y);
-      const bool h0 = t0 < INFINITY, h1 = t1 < INFINITY;
-      if (h0 && h1) {
-        const bool first0 = t0 <= t1;
-        st.push(first0 ? c1 : c0);
-        node = first0 ? c0 : c1;
-        continue;
-      }
-      if (h0) {
-        node = c0;
-        continue;
-      }
-      if (h1) {
-        node = c1;
-        continue;
-      }
-    } else {
-      const int code = ~node;
-      const int first = code >> 2, count = (code & 3) + 1;
-      if (first + count > sc.T) {
-        st.overflow = true;
-        return;
-      }
-      for (int k = 0; k < count; ++k) {
-        const int r = first + k;
-        int id;
-        const float t = tri_t(sc.tris, r, o, d, tmin, limit(), &id);
-        if (COUNT) ++ntris;
-        if (accept(t, r, id)) return;
-      }
-    }
-    if (st.sp == 0) return;
-    node = st.pop();
-  }
-  st.overflow = true;
-#endif
 }
 
 __device__ inline void add_work(Counters* ctr, int slot, uint32_t v) {

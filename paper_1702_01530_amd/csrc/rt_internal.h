@@ -15,12 +15,15 @@ namespace srt {
 // Device scene view (passed by value as a kernel argument)
 // ---------------------------------------------------------------------------------------------
 //
-// BVH2 node (width 2), 64 bytes = 4 x float4:
-//   n[0] = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
-//   n[1] = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
-//   n[2] = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
-//   n[3] = (child0, child1, -, -) as int bits
-// BVH4 node (width 4), 128 bytes = 8 x float4, one lane per child:
+// BVH4 node, 64 bytes = 4 x float4 (quantised child boxes, the default):
+//   n[0] = (p.x, p.y, p.z, e) with p the node's lower corner and e = three biased exponents
+//          (bits 0-7: x, 8-15: y, 16-23: z) of the per-axis steps s = 2^(e - 127)
+//   n[1] = child references as int bits
+//   n[2] = (lo.x, hi.x, lo.y, hi.y), n[3] = (lo.z, hi.z, 0, 0): 8-bit grid coordinates, child k in
+//          byte k; child k's box on an axis is [p + lo_k s, p + hi_k s] (exact values), which
+//          contains its padded FP32 box.  An empty slot has lo = 255 > hi = 0 on every axis and
+//          repeats child 0's reference, so even a spurious entry only revisits child 0.
+// BVH4 node with FP32 child boxes (SRT_QNODE=0), 128 bytes = 8 x float4, one lane per child:
 //   n[0..5] = lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of children 0..3
 //   n[6]    = child references as int bits;  n[7] unused
 //   an empty child slot has a box at +inf on every axis (never entered).
@@ -35,13 +38,13 @@ namespace srt {
 // Primitive keys inside the kernels: triangle record index [0,T), sphere T+s, plane T+S+p.
 // Output ids are the input order (a record carries its original id).
 
-#ifndef SRT_BVH_WIDTH
-#define SRT_BVH_WIDTH 4
+#ifndef SRT_QNODE
+#define SRT_QNODE 1
 #endif
-constexpr int kNodeWidth = SRT_BVH_WIDTH;        // 2: 64-byte BVH2 nodes; 4: 128-byte BVH4 nodes
-constexpr int kNodeFloat4 = kNodeWidth == 2 ? 4 : 8;
+constexpr bool kQuantNodes = SRT_QNODE != 0;
+constexpr int kNodeWidth = 4;
+constexpr int kNodeFloat4 = kQuantNodes ? 4 : 8;
 constexpr int kNodeBytes = 16 * kNodeFloat4;
-static_assert(kNodeWidth == 2 || kNodeWidth == 4, "BVH width must be 2 or 4");
 constexpr int kLeafMaxTris = 4;
 constexpr int kTriFloat4 = 3;
 constexpr int kMatFloat4 = 3;    // (kd, n), (ks, 0), (kr, 0)

@@ -65,6 +65,7 @@ class GpuScene:
         self.desc = d
         storage, scratch = rt.rt_scene_storage_size(d)
         self._storage, sptr = aligned_buffer(storage, self.device)
+        self.storage_offset = sptr - self._storage.data_ptr()  # where the built scene starts in _storage
         scratch_t, kptr = aligned_buffer(scratch, self.device)
         self.storage_bytes, self.scratch_bytes = storage, scratch
         self.handle = rt.rt_scene_build(d, sptr, storage, kptr, scratch, stream_handle(stream))

@@ -350,6 +350,11 @@ def test_invalid_arguments_gpu(torch_cuda):
     with pytest.raises(rt.RtError) as ei:
         GpuScene(bad)
     assert ei.value.status == rt.RT_ERR_INVALID_ARGUMENT and "finite" in str(ei.value)
+    bad = make_scene(tris=scene.triangles.copy())
+    bad.triangles[5, 2, 0] = -2e18  # finite but beyond the largest supported coordinate
+    with pytest.raises(rt.RtError) as ei:
+        GpuScene(bad)
+    assert ei.value.status == rt.RT_ERR_INVALID_ARGUMENT and "magnitude" in str(ei.value)
     bad = make_scene(tris=scene.triangles, tri_mat=np.full(scene.num_triangles, 7))
     with pytest.raises(rt.RtError) as ei:
         GpuScene(bad)
@@ -359,18 +364,79 @@ def test_invalid_arguments_gpu(torch_cuda):
         GpuScene(bad)
 
 
+def _decode_children(rec: np.ndarray):
+    """Child boxes (lo [3,4], hi [3,4], FP64 exact values), references [4] and a validity mask [4] of one
+    BVH4 node record (128-byte FP32 layout or 64-byte quantised layout)."""
+    f, u = rec.view(np.float32), rec.view(np.uint32)
+    if rec.nbytes == 128:
+        lo = f[0:24].reshape(6, 4)[0::2].astype(np.float64)
+        hi = f[0:24].reshape(6, 4)[1::2].astype(np.float64)
+        refs = u[24:28].view(np.int32)
+        valid = np.isfinite(lo).all(axis=0)
+        return lo, hi, refs, valid
+    assert rec.nbytes == 64
+    p = f[0:3].astype(np.float64)
+    e = np.array([(int(u[3]) >> (8 * a)) & 0xFF for a in range(3)]) - 127
+    step = np.ldexp(1.0, e)
+    refs = u[4:8].view(np.int32)
+    words = [(u[8], u[9]), (u[10], u[11]), (u[12], u[13])]
+    qlo = np.array([[(int(w[0]) >> (8 * k)) & 0xFF for k in range(4)] for w in words], np.float64)
+    qhi = np.array([[(int(w[1]) >> (8 * k)) & 0xFF for k in range(4)] for w in words], np.float64)
+    valid = (qlo <= qhi).all(axis=0)
+    return p[:, None] + qlo * step[:, None], p[:, None] + qhi * step[:, None], refs, valid
+
+
 def test_bvh_structure(torch_cuda):
+    """Reads the built tree back and walks it: every node is reached once, every triangle is in exactly
+    one leaf, and every child's box (as the traversal sees it) contains the triangles under it."""
+    import torch
     from paper_1702_01530_amd.stereo import GpuScene
     scene, _ = sg.make_small_terrain(seed=3, grid=48, n_spheres=8, level=2)
     gs = GpuScene(scene)
     info = gs.info()
     T = scene.num_triangles
-    # a 4-wide tree collapsed from the T-1 binary nodes: between (T-1)/3 and T-1 nodes of 128 bytes
-    assert (T - 1) / 3 <= info["num_nodes"] <= T - 1 and info["node_bytes"] == 128 * info["num_nodes"]
+    n_nodes = info["num_nodes"]
+    rec_bytes = info["node_bytes"] // n_nodes
+    # a 4-wide tree collapsed from the T-1 binary nodes: between (T-1)/3 and T-1 nodes
+    assert (T - 1) / 3 <= n_nodes <= T - 1 and rec_bytes in (64, 128) and info["node_bytes"] == rec_bytes * n_nodes
     assert math.log(T, 4) <= info["bvh_depth"] <= 40
     lo, hi = scene.triangles.reshape(-1, 3).min(0), scene.triangles.reshape(-1, 3).max(0)
     assert np.array_equal(np.array(info["bounds_lo"], np.float32), lo)
     assert np.array_equal(np.array(info["bounds_hi"], np.float32), hi)
+
+    torch.cuda.synchronize()
+    raw = gs._storage[gs.storage_offset:].cpu().numpy()
+    nodes = raw[:n_nodes * rec_bytes].reshape(n_nodes, rec_bytes)
+    tris_off = -(-((T - 1) * rec_bytes) // 256) * 256
+    rec_ids = raw[tris_off:tris_off + 48 * T].view(np.int32).reshape(T, 12)[:, 3]
+    tri = scene.triangles.astype(np.float64)
+    seen_nodes = np.zeros(n_nodes, np.int32)
+    seen_tris = np.zeros(T, np.int32)
+    # entries: (node, intersection of the boxes entered on the way down)
+    stack = [(0, np.full(3, -np.inf), np.full(3, np.inf))]
+    while stack:
+        i, plo, phi = stack.pop()
+        seen_nodes[i] += 1
+        clo, chi, refs, valid = _decode_children(nodes[i])
+        assert valid[0]
+        for k in range(4):
+            if not valid[k]:
+                continue
+            blo, bhi = np.maximum(plo, clo[:, k]), np.minimum(phi, chi[:, k])
+            r = int(refs[k])
+            if r >= 0:
+                assert r < n_nodes
+                stack.append((r, blo, bhi))
+                continue
+            code = ~r
+            first, count = code >> 2, (code & 3) + 1
+            assert first + count <= T
+            for j in range(first, first + count):
+                seen_tris[j] += 1
+                v = tri[rec_ids[j]]
+                assert np.all(v >= blo) and np.all(v <= bhi), (i, k, j)
+    assert np.all(seen_nodes == 1) and np.all(seen_tris == 1)
+    assert np.array_equal(np.sort(rec_ids), np.arange(T))
     gs.close()
 
 
