@@ -1,21 +1,27 @@
 // Linear BVH build on the device (gfx950).
 //
 // The paper (Section 3, Table 1) lists BVH trees as fast to construct, simple to
-// traverse and well suited to GPUs.  The tree here is a linear BVH:
+// traverse and well suited to GPUs.  The tree here is built from the Morton order:
 //   1. per triangle: bounding box and centroid, input validation;
 //   2. reduction of the centroid and scene bounds;
 //   3. 63-bit Morton code of the centroid quantised to 2^21 cells per axis;
 //   4. stable LSD radix sort of (code, triangle id), 8 passes of 8 bits;
-//   5. Karras (2012) emission of the T-1 internal nodes of a binary tree from the
-//      sorted codes (split at the highest differing bit; equal codes split by index);
-//   6. bottom-up box refit (an atomic arrival counter per node, the second
+//   5. binary tree over the sorted leaves: by default locally-ordered clustering
+//      (PLOC: neighbours in the Morton order merge by smallest surface area, so
+//      node boxes come with the merges); with SRT_PLOC=0, Karras (2012) emission
+//      (split at the highest differing bit; equal codes split by index) followed by
+//   6. a bottom-up box refit (an atomic arrival counter per node, the second
 //      child to arrive unions both boxes and climbs on);
 //   7. top-down collapse into a 4-wide tree, one level per launch, with the
 //      children's boxes quantised to 8 bits on each node's own grid (64-byte
 //      nodes), and 48-byte triangle records in leaf order.
-// No SAH.  Every step is deterministic, so a scene always builds the same tree.
+// Every step is deterministic, so a scene always builds the same tree.
 
 #include <hip/hip_runtime.h>
+
+#ifndef SRT_PLOC
+#define SRT_PLOC 1
+#endif
 
 #include <algorithm>
 #include <cmath>
@@ -404,6 +410,120 @@ __global__ __launch_bounds__(kBlock) void k_refit(const int2* __restrict__ child
 }
 
 // ---------------------------------------------------------------------------------------------
+// 5'-6'. PLOC: parallel locally-ordered clustering over the Morton order (Meister and Bittner
+// 2018), an alternative to steps 5-6.  Clusters start as the sorted leaves.  Each round, every
+// cluster finds the neighbour within kPlocRadius positions whose merged box has the smallest
+// surface area (ties to the smaller position); mutual pairs merge into a new internal node, and
+// the survivors are compacted in order.  The globally best pair is always mutual, so every round
+// merges.  Node indices are handed out from T-2 downwards by prefix sums, so the root is node 0 and
+// the tree is the same on every run.
+// ---------------------------------------------------------------------------------------------
+
+constexpr int kPlocRadius = 16;
+
+__device__ inline float merged_area(float4 alo, float4 ahi, float4 blo, float4 bhi) {
+  const float dx = fmaxf(ahi.x, bhi.x) - fminf(alo.x, blo.x);
+  const float dy = fmaxf(ahi.y, bhi.y) - fminf(alo.y, blo.y);
+  const float dz = fmaxf(ahi.z, bhi.z) - fminf(alo.z, blo.z);
+  return dx * dy + dy * dz + dz * dx;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ploc_init(const uint32_t* __restrict__ sorted_ids,
+                                                      const float4* __restrict__ leaf_lo,
+                                                      const float4* __restrict__ leaf_hi, int64_t n,
+                                                      float4* __restrict__ c_lo, float4* __restrict__ c_hi,
+                                                      int32_t* __restrict__ c_ref) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t id = sorted_ids[i];
+  c_lo[i] = leaf_lo[id];
+  c_hi[i] = leaf_hi[id];
+  c_ref[i] = ~int32_t(i);
+}
+
+// nn[i] = the best merge partner of cluster i among positions i-R..i+R (n >= 2).
+__global__ __launch_bounds__(kBlock) void k_ploc_nn(const float4* __restrict__ c_lo, const float4* __restrict__ c_hi,
+                                                    int64_t n, int32_t* __restrict__ nn) {
+  __shared__ float4 s_lo[kBlock + 2 * kPlocRadius], s_hi[kBlock + 2 * kPlocRadius];
+  const int64_t start = int64_t(blockIdx.x) * kBlock;
+  for (int k = threadIdx.x; k < kBlock + 2 * kPlocRadius; k += kBlock) {
+    const int64_t g = start - kPlocRadius + k;
+    if (g >= 0 && g < n) {
+      s_lo[k] = c_lo[g];
+      s_hi[k] = c_hi[g];
+    }
+  }
+  __syncthreads();
+  const int64_t i = start + threadIdx.x;
+  if (i >= n) return;
+  const int si = threadIdx.x + kPlocRadius;
+  const float4 alo = s_lo[si], ahi = s_hi[si];
+  float best = INFINITY;
+  int32_t bj = int32_t(i > 0 ? i - 1 : i + 1);
+  for (int k = -kPlocRadius; k <= kPlocRadius; ++k) {  // ascending positions: ties keep the smaller one
+    const int64_t j = i + k;
+    if (k == 0 || j < 0 || j >= n) continue;
+    const float ar = merged_area(alo, ahi, s_lo[si + k], s_hi[si + k]);
+    if (ar < best) {
+      best = ar;
+      bj = int32_t(j);
+    }
+  }
+  nn[i] = bj;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ploc_flags(const int32_t* __restrict__ nn, int64_t n,
+                                                       uint32_t* __restrict__ keep, uint32_t* __restrict__ merge) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t j = nn[i];
+  const bool mutual = nn[j] == int32_t(i);
+  merge[i] = (mutual && int64_t(j) > i) ? 1u : 0u;  // the lower position of a mutual pair makes the node
+  keep[i] = (mutual && int64_t(j) < i) ? 0u : 1u;   // the higher one is absorbed
+}
+
+struct PlocCompactArgs {
+  const float4* c_lo;
+  const float4* c_hi;
+  const int32_t* c_ref;
+  const int32_t* nn;
+  const uint32_t* keep_pos;   // exclusive prefix sums of the keep flags
+  const uint32_t* merge_pos;  // ... and of the merge flags
+  int64_t n;
+  int64_t node_base;  // index of this round's first new node
+  float4* o_lo;
+  float4* o_hi;
+  int32_t* o_ref;
+  int2* children;
+  float4* nodebox;
+};
+
+__global__ __launch_bounds__(kBlock) void k_ploc_compact(PlocCompactArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  const int32_t j = a.nn[i];
+  const bool mutual = a.nn[j] == int32_t(i);
+  if (mutual && int64_t(j) < i) return;  // absorbed by cluster j
+  const uint32_t p = a.keep_pos[i];
+  if (mutual) {
+    const int64_t node = a.node_base + a.merge_pos[i];
+    const float4 alo = a.c_lo[i], ahi = a.c_hi[i], blo = a.c_lo[j], bhi = a.c_hi[j];
+    const float4 ulo = make_float4(fminf(alo.x, blo.x), fminf(alo.y, blo.y), fminf(alo.z, blo.z), 0.f);
+    const float4 uhi = make_float4(fmaxf(ahi.x, bhi.x), fmaxf(ahi.y, bhi.y), fmaxf(ahi.z, bhi.z), 0.f);
+    a.children[node] = make_int2(a.c_ref[i], a.c_ref[j]);
+    a.nodebox[2 * node] = ulo;
+    a.nodebox[2 * node + 1] = uhi;
+    a.o_lo[p] = ulo;
+    a.o_hi[p] = uhi;
+    a.o_ref[p] = int32_t(node);
+  } else {
+    a.o_lo[p] = a.c_lo[i];
+    a.o_hi[p] = a.c_hi[i];
+    a.o_ref[p] = a.c_ref[i];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // 7. Collapse into a 4-wide BVH, top-down one level at a time.  A BVH4 node takes a binary node's two
 // children and, while it has fewer than four, replaces its largest-area internal child by that
 // child's two children (keeping left-to-right order).  Internal children become the next level's
@@ -643,6 +763,16 @@ BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool
     p.frontier_off[1] = take(size_t(T) * 8);
     p.sel_off = take(size_t(T) * 16);
     p.nint_off = take(size_t(T + 1) * 4);
+#if SRT_PLOC
+    for (int k = 0; k < 2; ++k) {
+      p.ploc_lo_off[k] = take(size_t(T) * 16);
+      p.ploc_hi_off[k] = take(size_t(T) * 16);
+      p.ploc_ref_off[k] = take(size_t(T) * 4);
+    }
+    p.ploc_nn_off = take(size_t(T) * 4);
+    p.ploc_keep_off = take(size_t(T + 1) * 4);
+    p.ploc_merge_off = take(size_t(T + 1) * 4);
+#endif
   }
   p.scratch_bytes = off;
   return p;
@@ -754,6 +884,65 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
       int32_t* parent = reinterpret_cast<int32_t*>(scratch + plan.parent_off);
       uint32_t* flags = reinterpret_cast<uint32_t*>(scratch + plan.flags_off);
       float4* nodebox = reinterpret_cast<float4*>(scratch + plan.nodebox_off);
+#if SRT_PLOC
+      (void)range;
+      (void)parent;
+      (void)flags;
+      {
+        float4* c_lo[2] = {reinterpret_cast<float4*>(scratch + plan.ploc_lo_off[0]),
+                           reinterpret_cast<float4*>(scratch + plan.ploc_lo_off[1])};
+        float4* c_hi[2] = {reinterpret_cast<float4*>(scratch + plan.ploc_hi_off[0]),
+                           reinterpret_cast<float4*>(scratch + plan.ploc_hi_off[1])};
+        int32_t* c_ref[2] = {reinterpret_cast<int32_t*>(scratch + plan.ploc_ref_off[0]),
+                             reinterpret_cast<int32_t*>(scratch + plan.ploc_ref_off[1])};
+        int32_t* nn = reinterpret_cast<int32_t*>(scratch + plan.ploc_nn_off);
+        uint32_t* keep = reinterpret_cast<uint32_t*>(scratch + plan.ploc_keep_off);
+        uint32_t* merge = reinterpret_cast<uint32_t*>(scratch + plan.ploc_merge_off);
+        k_ploc_init<<<blocks_for(T), kBlock, 0, stream>>>(i0, lo, hi, T, c_lo[0], c_hi[0], c_ref[0]);
+        SRT_LAUNCH_CHECK();
+        int64_t n = T, next = T - 1;
+        int cur = 0;
+        for (int round = 0; n > 1; ++round) {
+          if (round > 100000) return hipErrorUnknown;  // every round merges at least one pair
+          k_ploc_nn<<<blocks_for(n), kBlock, 0, stream>>>(c_lo[cur], c_hi[cur], n, nn);
+          SRT_LAUNCH_CHECK();
+          k_ploc_flags<<<blocks_for(n), kBlock, 0, stream>>>(nn, n, keep, merge);
+          SRT_LAUNCH_CHECK();
+          k_scan_exclusive<<<1, 1024, 0, stream>>>(keep, n, keep + n);
+          SRT_LAUNCH_CHECK();
+          k_scan_exclusive<<<1, 1024, 0, stream>>>(merge, n, merge + n);
+          SRT_LAUNCH_CHECK();
+          uint32_t totals[2] = {0u, 0u};
+          SRT_CHECK(hipMemcpyAsync(&totals[0], keep + n, 4, hipMemcpyDeviceToHost, stream));
+          SRT_CHECK(hipMemcpyAsync(&totals[1], merge + n, 4, hipMemcpyDeviceToHost, stream));
+          SRT_CHECK(hipStreamSynchronize(stream));
+          const int64_t merges = totals[1];
+          if (merges < 1 || merges > next || int64_t(totals[0]) != n - merges) return hipErrorUnknown;
+          PlocCompactArgs ca;
+          ca.c_lo = c_lo[cur];
+          ca.c_hi = c_hi[cur];
+          ca.c_ref = c_ref[cur];
+          ca.nn = nn;
+          ca.keep_pos = keep;
+          ca.merge_pos = merge;
+          ca.n = n;
+          ca.node_base = next - merges;
+          ca.o_lo = c_lo[cur ^ 1];
+          ca.o_hi = c_hi[cur ^ 1];
+          ca.o_ref = c_ref[cur ^ 1];
+          ca.children = children;
+          ca.nodebox = nodebox;
+          k_ploc_compact<<<blocks_for(n), kBlock, 0, stream>>>(ca);
+          SRT_LAUNCH_CHECK();
+          next -= merges;
+          n -= merges;
+          cur ^= 1;
+        }
+        if (next != 0) return hipErrorUnknown;  // T - 1 merges make a binary tree rooted at node 0
+      }
+      SRT_CHECK(hipMemcpyAsync(&bounds, partial, sizeof(bounds), hipMemcpyDeviceToHost, stream));
+      SRT_CHECK(hipStreamSynchronize(stream));
+#else
       int32_t* dmax = reinterpret_cast<int32_t*>(status + 4);
       k_karras<<<blocks_for(T - 1), kBlock, 0, stream>>>(k0, T, children, parent, range);
       SRT_LAUNCH_CHECK();
@@ -765,6 +954,7 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
       SRT_CHECK(hipMemcpyAsync(&bounds, partial, sizeof(bounds), hipMemcpyDeviceToHost, stream));
       SRT_CHECK(hipMemcpyAsync(&depth, dmax, sizeof(depth), hipMemcpyDeviceToHost, stream));
       SRT_CHECK(hipStreamSynchronize(stream));
+#endif
       float coord_max = 0.f;
       for (int a = 0; a < 3; ++a)
         coord_max = std::max(coord_max, std::max(std::fabs(bounds.blo[a]), std::fabs(bounds.bhi[a])));
