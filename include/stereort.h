@@ -193,9 +193,9 @@ enum {
   RT_FLAG_PATH_IDS = 1u << 0,   /* write path_prims / shadow_state */
   RT_FLAG_COUNT_WORK = 1u << 1, /* count node visits and triangle tests (slower kernels) */
   RT_FLAG_BRUTE_FORCE = 1u << 2, /* test every triangle even if the scene has a BVH */
-  RT_FLAG_READBACK_MEMCPY = 1u << 3 /* read back with hipMemcpyAsync.  By default a narrow copy kernel
-                                       writes through the pinned buffer's device view (hipMemcpyAsync is
-                                       used when host_radiance has none) */
+  RT_FLAG_READBACK_KERNEL = 1u << 3 /* read back through a narrow copy kernel writing through the pinned
+                                       buffer's device view (when it has one) instead of the default
+                                       hipMemcpyAsync */
 };
 
 /* Device workspace bytes for rendering a whole stereo frame of `camera` with

@@ -220,7 +220,7 @@ rt_status check_output(const rt_stereo_output* o, uint32_t flags) {
   return RT_OK;
 }
 
-constexpr uint32_t kKnownFlags = RT_FLAG_PATH_IDS | RT_FLAG_COUNT_WORK | RT_FLAG_BRUTE_FORCE | RT_FLAG_READBACK_MEMCPY;
+constexpr uint32_t kKnownFlags = RT_FLAG_PATH_IDS | RT_FLAG_COUNT_WORK | RT_FLAG_BRUTE_FORCE | RT_FLAG_READBACK_KERNEL;
 constexpr int kReadbackBlocks = 32;
 
 srt::DevOutputs dev_outputs(const rt_stereo_output* o, uint32_t flags) {
@@ -252,12 +252,10 @@ rt_status readback(const rt_stereo_camera* cam, const rt_stereo_output* out, uin
     (void)hipEventDestroy(ev);
     if (e != hipSuccess) return hip_fail(e, "stream ordering for readback");
   }
-  // Default: a narrow copy kernel writes through the pinned buffer's device view, so the copy
-  // does not crowd the next frame's traversal off the compute units (hipMemcpyAsync's blit
-  // kernel does).  hipMemcpyAsync is used with RT_FLAG_READBACK_MEMCPY or when the buffer has
-  // no device view (not pinned and mapped).
+  // Default: hipMemcpyAsync.  With RT_FLAG_READBACK_KERNEL a narrow copy kernel (a few
+  // workgroups) writes through the pinned buffer's device view instead, when the buffer has one.
   void* dview[2] = {nullptr, nullptr};
-  bool use_kernel = (flags & RT_FLAG_READBACK_MEMCPY) == 0;
+  bool use_kernel = (flags & RT_FLAG_READBACK_KERNEL) != 0;
   for (int eye = 0; eye < 2 && use_kernel; ++eye)
     if (hipHostGetDevicePointer(&dview[eye], out->host_radiance[eye], 0) != hipSuccess || !dview[eye]) {
       (void)hipGetLastError();

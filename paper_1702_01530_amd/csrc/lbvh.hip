@@ -259,6 +259,58 @@ __global__ __launch_bounds__(1024) void k_scan_exclusive(uint32_t* __restrict__ 
   if (total_out && tid == 1023) *total_out = part[1023];
 }
 
+// Multi-block exclusive scan for long arrays: per-tile sums, a scan of the sums, then each tile
+// scans itself from its offset.  Tiles are kScanTile consecutive elements, 4 per thread.
+constexpr int kScanThreads = 1024, kScanPer = 4, kScanTile = kScanThreads * kScanPer;
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_sums(const uint32_t* __restrict__ data, int64_t m,
+                                                             uint32_t* __restrict__ sums) {
+  __shared__ uint32_t red[kScanThreads / 64];
+  const int64_t base = int64_t(blockIdx.x) * kScanTile;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int64_t i = base + threadIdx.x + int64_t(k) * kScanThreads;
+    if (i < m) s += data[i];
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) t += red[w];
+    sums[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint32_t* __restrict__ data, int64_t m,
+                                                             const uint32_t* __restrict__ offsets) {
+  __shared__ uint32_t part[kScanThreads];
+  const int tid = threadIdx.x;
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(tid) * kScanPer;
+  uint32_t v[kScanPer];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = base + k < m ? data[base + k] : 0u;
+    s += v[k];
+  }
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t x = tid >= off ? part[tid - off] : 0u;
+    __syncthreads();
+    part[tid] += x;
+    __syncthreads();
+  }
+  uint32_t run = offsets[blockIdx.x] + part[tid] - s;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < m) data[base + k] = run;
+    run += v[k];
+  }
+}
+
 __device__ inline uint64_t lanemask_lt() {
   const int lane = threadIdx.x & 63;
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -419,7 +471,10 @@ __global__ __launch_bounds__(kBlock) void k_refit(const int2* __restrict__ child
 // the tree is the same on every run.
 // ---------------------------------------------------------------------------------------------
 
-constexpr int kPlocRadius = 16;
+#ifndef SRT_PLOC_RADIUS
+#define SRT_PLOC_RADIUS 16
+#endif
+constexpr int kPlocRadius = SRT_PLOC_RADIUS;
 
 __device__ inline float merged_area(float4 alo, float4 ahi, float4 blo, float4 bhi) {
   const float dx = fmaxf(ahi.x, bhi.x) - fminf(alo.x, blo.x);
@@ -647,7 +702,8 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(WideArgs a) {
         phi[ax] = fmaxf(phi[ax], hi[ax][k]);
       }
   }
-  uint32_t qlo[3] = {0u, 0u, 0u}, qhi[3] = {0u, 0u, 0u}, ebits = 0u;
+  uint32_t qlo[3] = {0u, 0u, 0u}, qhi[3] = {0u, 0u, 0u};
+  float steps[3];
   for (int ax = 0; ax < 3; ++ax) {
     const double base = double(plo[ax]);
     const double ext = nextafter(double(phi[ax]) - base, INFINITY);
@@ -660,7 +716,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(WideArgs a) {
       while (ldexp(255.0, e) < ext) ++e;
     }
     const double step = ldexp(1.0, e);
-    ebits |= uint32_t(e + 127) << (8 * ax);
+    steps[ax] = __uint_as_float(uint32_t(e + 127) << 23);  // 2^e, a normal float
     for (int k = 0; k < 4; ++k) {
       uint32_t ql = 255u, qh = 0u;
       if (r[k] != kWideEmpty) {
@@ -676,10 +732,10 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(WideArgs a) {
   for (int k = 1; k < 4; ++k)
     if (r[k] == kWideEmpty) ref[k] = ref[0];
   float4* out = a.nodes + 4 * int64_t(b4);
-  out[0] = make_float4(plo[0], plo[1], plo[2], __uint_as_float(ebits));
+  out[0] = make_float4(plo[0], plo[1], plo[2], steps[0]);
   out[1] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), __int_as_float(ref[2]), __int_as_float(ref[3]));
   out[2] = make_float4(__uint_as_float(qlo[0]), __uint_as_float(qhi[0]), __uint_as_float(qlo[1]), __uint_as_float(qhi[1]));
-  out[3] = make_float4(__uint_as_float(qlo[2]), __uint_as_float(qhi[2]), 0.f, 0.f);
+  out[3] = make_float4(__uint_as_float(qlo[2]), __uint_as_float(qhi[2]), steps[1], steps[2]);
 #else
   float4* out = a.nodes + 8 * int64_t(b4);
   out[0] = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
@@ -717,6 +773,22 @@ __global__ void k_fill(T* p, T v, int64_t n) {
 inline unsigned blocks_for(int64_t n, int b = kBlock) { return unsigned((n + b - 1) / b); }
 
 }  // namespace
+
+// In-place exclusive scan of data[0, m); the total goes to *total_out if it is not null.  `tmp`
+// holds scan_tmp_entries(m) words.
+int64_t scan_tmp_entries(int64_t m) { return m / kScanTile + 2; }
+
+hipError_t scan_exclusive(uint32_t* data, int64_t m, uint32_t* total_out, uint32_t* tmp, hipStream_t s) {
+  if (m <= 2 * kScanTile) {
+    k_scan_exclusive<<<1, 1024, 0, s>>>(data, m, total_out);
+    return hipGetLastError();
+  }
+  const int64_t nb = (m + kScanTile - 1) / kScanTile;
+  k_tile_sums<<<unsigned(nb), kScanThreads, 0, s>>>(data, m, tmp);
+  k_scan_exclusive<<<1, 1024, 0, s>>>(tmp, nb, total_out);
+  k_tile_scan<<<unsigned(nb), kScanThreads, 0, s>>>(data, m, tmp);
+  return hipGetLastError();
+}
 
 BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool bvh) {
   BuildPlan p{};
@@ -763,6 +835,7 @@ BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool
     p.frontier_off[1] = take(size_t(T) * 8);
     p.sel_off = take(size_t(T) * 16);
     p.nint_off = take(size_t(T + 1) * 4);
+    p.scan_tmp_off = take(size_t(scan_tmp_entries(std::max<int64_t>(T + 1, p.num_sort_blocks * kRadix))) * 4);
 #if SRT_PLOC
     for (int k = 0; k < 2; ++k) {
       p.ploc_lo_off[k] = take(size_t(T) * 16);
@@ -864,6 +937,7 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
       uint32_t* i0 = reinterpret_cast<uint32_t*>(scratch + plan.ids0_off);
       uint32_t* i1 = reinterpret_cast<uint32_t*>(scratch + plan.ids1_off);
       uint32_t* hist = reinterpret_cast<uint32_t*>(scratch + plan.hist_off);
+      uint32_t* scan_tmp = reinterpret_cast<uint32_t*>(scratch + plan.scan_tmp_off);
       k_morton<<<blocks_for(T), kBlock, 0, stream>>>(lo, hi, partial, T, k0, i0);
       SRT_LAUNCH_CHECK();
       const int64_t nb = plan.num_sort_blocks;
@@ -871,8 +945,7 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
         int shift = pass * kRadixBits;
         k_digit_hist<<<unsigned(nb), kBlock, 0, stream>>>(k0, T, shift, hist, nb);
         SRT_LAUNCH_CHECK();
-        k_scan_exclusive<<<1, 1024, 0, stream>>>(hist, nb * kRadix, nullptr);
-        SRT_LAUNCH_CHECK();
+        SRT_CHECK(scan_exclusive(hist, nb * kRadix, nullptr, scan_tmp, stream));
         k_scatter<<<unsigned(nb), kBlock, 0, stream>>>(k0, i0, T, shift, hist, nb, k1, i1);
         SRT_LAUNCH_CHECK();
         std::swap(k0, k1);
@@ -908,10 +981,8 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
           SRT_LAUNCH_CHECK();
           k_ploc_flags<<<blocks_for(n), kBlock, 0, stream>>>(nn, n, keep, merge);
           SRT_LAUNCH_CHECK();
-          k_scan_exclusive<<<1, 1024, 0, stream>>>(keep, n, keep + n);
-          SRT_LAUNCH_CHECK();
-          k_scan_exclusive<<<1, 1024, 0, stream>>>(merge, n, merge + n);
-          SRT_LAUNCH_CHECK();
+          SRT_CHECK(scan_exclusive(keep, n, keep + n, scan_tmp, stream));
+          SRT_CHECK(scan_exclusive(merge, n, merge + n, scan_tmp, stream));
           uint32_t totals[2] = {0u, 0u};
           SRT_CHECK(hipMemcpyAsync(&totals[0], keep + n, 4, hipMemcpyDeviceToHost, stream));
           SRT_CHECK(hipMemcpyAsync(&totals[1], merge + n, 4, hipMemcpyDeviceToHost, stream));
@@ -981,8 +1052,7 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
         wa.level_base = allocated;
         k_wide_select<<<blocks_for(m), kBlock, 0, stream>>>(wa);
         SRT_LAUNCH_CHECK();
-        k_scan_exclusive<<<1, 1024, 0, stream>>>(wa.nint, m, wa.nint + m);
-        SRT_LAUNCH_CHECK();
+        SRT_CHECK(scan_exclusive(wa.nint, m, wa.nint + m, scan_tmp, stream));
         k_wide_emit<<<blocks_for(m), kBlock, 0, stream>>>(wa);
         SRT_LAUNCH_CHECK();
         uint32_t next_m = 0;

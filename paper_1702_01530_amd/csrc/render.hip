@@ -220,12 +220,8 @@ __device__ __attribute__((always_inline)) inline void node4_children(const float
   // Slab planes of child k on axis a are p_a + q s_a, i.e. t = q (s_a / d_a) + (p_a - o_a) / d_a; the
   // near and far planes of an axis are picked once per node from the ray's direction sign.
   const float4* n = nodes + 4 * node;
-  const float4 n0 = n[0], n1 = n[1], n2 = n[2];
-  const float2 n3 = reinterpret_cast<const float2*>(n)[6];
-  const uint32_t eb = __float_as_uint(n0.w);
-  const float ax = __uint_as_float((eb << 23) & 0x7f800000u) * inv.x;
-  const float ay = __uint_as_float((eb << 15) & 0x7f800000u) * inv.y;
-  const float az = __uint_as_float((eb << 7) & 0x7f800000u) * inv.z;
+  const float4 n0 = n[0], n1 = n[1], n2 = n[2], n3 = n[3];
+  const float ax = n0.w * inv.x, ay = n3.z * inv.y, az = n3.w * inv.z;  // steps are powers of two: exact
   const float bx = fmaf(n0.x, inv.x, -oi.x), by = fmaf(n0.y, inv.y, -oi.y), bz = fmaf(n0.z, inv.z, -oi.z);
   const bool px = inv.x >= 0.f, py = inv.y >= 0.f, pz = inv.z >= 0.f;
   const uint32_t qlx = __float_as_uint(n2.x), qhx = __float_as_uint(n2.y), qly = __float_as_uint(n2.z),

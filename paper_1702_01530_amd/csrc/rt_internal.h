@@ -16,11 +16,11 @@ namespace srt {
 // ---------------------------------------------------------------------------------------------
 //
 // BVH4 node, 64 bytes = 4 x float4 (quantised child boxes, the default):
-//   n[0] = (p.x, p.y, p.z, e) with p the node's lower corner and e = three biased exponents
-//          (bits 0-7: x, 8-15: y, 16-23: z) of the per-axis steps s = 2^(e - 127)
+//   n[0] = (p.x, p.y, p.z, s.x) with p the node's lower corner and s the per-axis grid steps,
+//          powers of two
 //   n[1] = child references as int bits
-//   n[2] = (lo.x, hi.x, lo.y, hi.y), n[3] = (lo.z, hi.z, 0, 0): 8-bit grid coordinates, child k in
-//          byte k; child k's box on an axis is [p + lo_k s, p + hi_k s] (exact values), which
+//   n[2] = (lo.x, hi.x, lo.y, hi.y), n[3] = (lo.z, hi.z, s.y, s.z): 8-bit grid coordinates, child k
+//          in byte k; child k's box on an axis is [p + lo_k s, p + hi_k s] (exact values), which
 //          contains its padded FP32 box.  An empty slot has lo = 255 > hi = 0 on every axis and
 //          repeats child 0's reference, so even a spurious entry only revisits child 0.
 // BVH4 node with FP32 child boxes (SRT_QNODE=0), 128 bytes = 8 x float4, one lane per child:
@@ -121,6 +121,7 @@ struct BuildPlan {
   size_t keys0_off, keys1_off, ids0_off, ids1_off, lo_off, hi_off, partial_off, hist_off, children_off,
       parent_off, flags_off, nodebox_off, status_off, range_off, frontier_off[2], sel_off, nint_off;
   size_t ploc_lo_off[2], ploc_hi_off[2], ploc_ref_off[2], ploc_nn_off, ploc_keep_off, ploc_merge_off;
+  size_t scan_tmp_off;
   size_t scratch_bytes;
   int64_t num_blocks_prep, num_sort_blocks;
   bool bvh;

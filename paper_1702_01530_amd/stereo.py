@@ -134,10 +134,10 @@ def output_struct(o: dict) -> rt.rt_stereo_output:
 
 def render_stereo(gs: GpuScene, cam, *, path_ids=False, count_work=False, brute_force=False, host=False,
                   workspace: Workspace | None = None, outputs: dict | None = None, stream=None, copy_stream=None,
-                  timer=None, readback_memcpy=False) -> dict:
+                  timer=None, readback_kernel=False) -> dict:
     """Renders both eyes; returns the output tensors (valid after the stream is synchronised)."""
     flags = (rt.RT_FLAG_PATH_IDS if path_ids else 0) | (rt.RT_FLAG_COUNT_WORK if count_work else 0) | (
-        rt.RT_FLAG_BRUTE_FORCE if brute_force else 0) | (rt.RT_FLAG_READBACK_MEMCPY if readback_memcpy else 0)
+        rt.RT_FLAG_BRUTE_FORCE if brute_force else 0) | (rt.RT_FLAG_READBACK_KERNEL if readback_kernel else 0)
     camst = rt.make_camera_struct(cam)
     if workspace is None:
         workspace = Workspace(rt.rt_render_workspace_size(camst, gs.num_lights), gs.device)
@@ -148,9 +148,9 @@ def render_stereo(gs: GpuScene, cam, *, path_ids=False, count_work=False, brute_
     return o
 
 
-def _flags(path_ids=False, count_work=False, brute_force=False, readback_memcpy=False) -> int:
+def _flags(path_ids=False, count_work=False, brute_force=False, readback_kernel=False) -> int:
     return (rt.RT_FLAG_PATH_IDS if path_ids else 0) | (rt.RT_FLAG_COUNT_WORK if count_work else 0) | (
-        rt.RT_FLAG_BRUTE_FORCE if brute_force else 0) | (rt.RT_FLAG_READBACK_MEMCPY if readback_memcpy else 0)
+        rt.RT_FLAG_BRUTE_FORCE if brute_force else 0) | (rt.RT_FLAG_READBACK_KERNEL if readback_kernel else 0)
 
 
 def batch_items(pairs, outs) -> C.Array:
@@ -169,10 +169,10 @@ def batch_outputs(pairs, path_ids=False, host=False) -> list:
 
 def render_batch(pairs, *, path_ids=False, count_work=False, brute_force=False, host=False,
                  workspace: Workspace | None = None, outputs: list | None = None, stream=None, timer=None,
-                 readback_memcpy=False) -> list:
+                 readback_kernel=False) -> list:
     """Renders a batch of (GpuScene, camera) pairs as one pipeline; returns one output dict per pair.
     The batch's total ray counts go to the first pair's ``ray_counts``."""
-    flags = _flags(path_ids, count_work, brute_force, readback_memcpy)
+    flags = _flags(path_ids, count_work, brute_force, readback_kernel)
     outs = outputs if outputs is not None else batch_outputs(pairs, path_ids, host)
     items = batch_items(pairs, outs)
     if workspace is None:
@@ -185,9 +185,9 @@ class BatchGraph:
     """A batch's render passes captured into a HIP graph; launch() replays them for any batch of the same
     shape (item count, sizes, depths, light counts) with new scenes, poses and outputs."""
 
-    def __init__(self, pairs, outputs: list, workspace: Workspace, *, path_ids=False, readback_memcpy=False,
+    def __init__(self, pairs, outputs: list, workspace: Workspace, *, path_ids=False, readback_kernel=False,
                  stream=None):
-        self.flags = _flags(path_ids=path_ids, readback_memcpy=readback_memcpy)
+        self.flags = _flags(path_ids=path_ids, readback_kernel=readback_kernel)
         self.workspace = workspace
         self._stream = stream if stream is not None else torch.cuda.Stream()
         items = batch_items(pairs, outputs)

@@ -325,15 +325,15 @@ def test_pinned_readback_and_timer(torch_cuda):
 
 
 @pytest.mark.parametrize("size", [(256, 256), (37, 23)])  # the second eye of 37x23 is not 16-byte aligned
-@pytest.mark.parametrize("memcpy", [False, True])
-def test_readback_matches_device(torch_cuda, size, memcpy):
+@pytest.mark.parametrize("kernel", [False, True])
+def test_readback_matches_device(torch_cuda, size, kernel):
     torch = torch_cuda
     from paper_1702_01530_amd.stereo import GpuScene, render_stereo
     scene, cam = sg.make_spheres_scene()
     cam = cam.resized(*size)
     gs = GpuScene(scene)
     copy = torch.cuda.Stream()
-    out = render_stereo(gs, cam, host=True, copy_stream=copy, readback_memcpy=memcpy)
+    out = render_stereo(gs, cam, host=True, copy_stream=copy, readback_kernel=kernel)
     copy.synchronize()
     torch.cuda.synchronize()
     assert torch.equal(out["host_radiance"], out["radiance"].cpu())
@@ -376,8 +376,8 @@ def _decode_children(rec: np.ndarray):
         return lo, hi, refs, valid
     assert rec.nbytes == 64
     p = f[0:3].astype(np.float64)
-    e = np.array([(int(u[3]) >> (8 * a)) & 0xFF for a in range(3)]) - 127
-    step = np.ldexp(1.0, e)
+    step = np.array([f[3], f[14], f[15]], np.float64)
+    assert np.all(np.frexp(step)[0] == 0.5)  # powers of two
     refs = u[4:8].view(np.int32)
     words = [(u[8], u[9]), (u[10], u[11]), (u[12], u[13])]
     qlo = np.array([[(int(w[0]) >> (8 * k)) & 0xFF for k in range(4)] for w in words], np.float64)
