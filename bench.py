@@ -397,7 +397,7 @@ def main():
         raise SystemExit("internal consistency check fired during the counting pass")
     rays = int(cnt[0] + cnt[1] + cnt[2])
     closest_rays, any_rays = int(cnt[0] + cnt[1]), int(cnt[2])
-    node_visit = NODE_VISIT_BYTES[info["node_bytes"] // max(info["num_nodes"], 1)]
+    node_visit = NODE_VISIT_BYTES.get(info["node_bytes"] // max(info["num_nodes"], 1), 0)  # 0: no BVH
     closest_bytes = node_visit * cnt[3] + TRI_BYTES * cnt[4] + CLOSEST_RAY_IO * closest_rays
     any_bytes = node_visit * cnt[5] + TRI_BYTES * cnt[6] + ANY_RAY_IO * any_rays
     log(f"[bench] rays/frame {rays} (primary {cnt[0]}, mirror {cnt[1]}, shadow {cnt[2]}); "

@@ -455,12 +455,19 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
   if (shadows)
     for (int l = 0; l < LS; ++l) total += round64(a.ctr->shadow_count[depth - 1][l]);
   uint32_t c_nodes = 0, c_tris = 0, s_nodes = 0, s_tris = 0;
-  while (true) {
-    // one wave-wide batch of 64 work items per atomic (larger grabs unbalance the launch's end, and
-    // refilling single lanes stalls the wave on every refill)
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(&a.ctr->trace_work[depth], 64u);
-    base = __shfl(base, 0);
+  // Work comes in wave-wide batches of 64 items (larger grabs unbalance the launch's end, and
+  // refilling single lanes stalls the wave on every refill).  Wave w's first batch is batch w, with
+  // no atomic; later batches come from one device-wide counter past the first round.  Device-scope
+  // atomics on one address serialise, so a launch whose work fits in the first round takes none.
+  const uint32_t first_round = gridDim.x * uint32_t(kWaves) * 64u;
+  uint32_t base = (blockIdx.x * uint32_t(kWaves) + uint32_t(threadIdx.x >> 6)) * 64u;
+  for (bool first = true;; first = false) {
+    if (!first) {
+      if (first_round >= total) break;
+      uint32_t grab = 0;
+      if (lane == 0) grab = atomicAdd(&a.ctr->trace_work[depth], 64u);
+      base = first_round + __shfl(grab, 0);
+    }
     if (base >= total) break;
     if (base < nc_pad) {
       // ---- closest-hit batch
