@@ -456,19 +456,24 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
     for (int l = 0; l < LS; ++l) total += round64(a.ctr->shadow_count[depth - 1][l]);
   uint32_t c_nodes = 0, c_tris = 0, s_nodes = 0, s_tris = 0;
   // Work comes in wave-wide batches of 64 items (larger grabs unbalance the launch's end, and
-  // refilling single lanes stalls the wave on every refill).  Wave w's first batch is batch w, with
-  // no atomic; later batches come from one device-wide counter past the first round.  Device-scope
-  // atomics on one address serialise, so a launch whose work fits in the first round takes none.
-  const uint32_t first_round = gridDim.x * uint32_t(kWaves) * 64u;
-  uint32_t base = (blockIdx.x * uint32_t(kWaves) + uint32_t(threadIdx.x >> 6)) * 64u;
+  // refilling single lanes stalls the wave on every refill).  Device-scope atomics on one address
+  // serialise, so: wave w's first batch is batch w, with no atomic (a launch whose work fits in
+  // the first round takes none); later batches b = nwaves + c + K k come from counter c = w mod K
+  // of K interleaved counters, so K atomics proceed at once.
+  const uint32_t nwaves = gridDim.x * uint32_t(kWaves);
+  const uint32_t wid = blockIdx.x * uint32_t(kWaves) + uint32_t(threadIdx.x >> 6);
+  const uint32_t nbatches = total / 64u;  // total is a multiple of 64
+  const uint32_t home = wid % uint32_t(kWorkCounters);
+  uint32_t batch = wid;
   for (bool first = true;; first = false) {
     if (!first) {
-      if (first_round >= total) break;
-      uint32_t grab = 0;
-      if (lane == 0) grab = atomicAdd(&a.ctr->trace_work[depth], 64u);
-      base = first_round + __shfl(grab, 0);
+      if (nwaves + home >= nbatches) break;  // no batch left for this counter
+      uint32_t k = 0;
+      if (lane == 0) k = atomicAdd(&a.ctr->trace_work[depth][home][0], 1u);
+      batch = nwaves + home + uint32_t(kWorkCounters) * __shfl(k, 0);
     }
-    if (base >= total) break;
+    if (batch >= nbatches) break;
+    const uint32_t base = batch * 64u;
     if (base < nc_pad) {
       // ---- closest-hit batch
       const uint32_t e = base + lane;

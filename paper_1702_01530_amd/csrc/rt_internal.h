@@ -93,11 +93,16 @@ struct DevItem {
   int64_t path_offset;
 };
 
+// Device-scope atomics on one address serialise; the traversal's work cursor is split into this
+// many counters, each serving an interleaved share of the batches.
+constexpr int kWorkCounters = 16;
+
 // Work counters inside the render workspace.
 struct Counters {
   uint32_t refl_count[RT_MAX_DEPTH + 2];                   // entries of the mirror-ray queue at depth d
   uint32_t shadow_count[RT_MAX_DEPTH + 2][RT_MAX_LIGHTS];  // shadow records of depth d towards light l
-  uint32_t trace_work[RT_MAX_DEPTH + 2];                   // persistent work cursor of the trace launch d
+  // work cursors of the trace launch of depth d, one per counter group, 256 bytes apart
+  uint32_t trace_work[RT_MAX_DEPTH + 2][kWorkCounters][64];
   uint32_t primary;                                        // valid primary paths
   uint32_t error;                                          // consistency-check hits
   unsigned long long work[4];                              // node visits / tri tests (closest, shadow)
