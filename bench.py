@@ -7,7 +7,9 @@ resident in HBM (the scene is built once) before the timed region starts.
 
 Prints one JSON line.  `value` is Mrays/s (all rays of the frame / device time
 per frame); stereo frames/s is reported beside it, device-only and end to end
-(including the pinned asynchronous readback of both eyes' radiance).
+(including the pinned asynchronous readback of both eyes' radiance).  Frames are
+rendered continuously with --frames-in-flight of them on their own streams (2 by
+default); the time per frame with one frame in flight is reported beside it.
 """
 from __future__ import annotations
 
@@ -338,6 +340,8 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="serving workload: number of requests")
     ap.add_argument("--rate", type=float, default=100.0, help="serving workload: Poisson arrival rate (1/s)")
     ap.add_argument("--no-end-to-end", action="store_true")
+    ap.add_argument("--frames-in-flight", type=int, default=2,
+                    help="frames rendered concurrently on their own streams (1: strictly one after another)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM traffic counters)")
     args = ap.parse_args()
@@ -404,59 +408,83 @@ def main():
         f"closest: {cnt[3] / max(closest_rays, 1):.1f} nodes + {cnt[4] / max(closest_rays, 1):.1f} tris per ray; "
         f"shadow: {cnt[5] / max(any_rays, 1):.1f} nodes + {cnt[6] / max(any_rays, 1):.1f} tris per ray")
 
-    for _ in range(args.warmup):
-        render_stereo(gs, cam, workspace=ws, outputs=out)
-    torch.cuda.synchronize()
+    # Frames are rendered round-robin over F streams (frames in flight), each with its own workspace
+    # and outputs, the way a renderer runs continuously: the small, latency-bound launches at the end
+    # of one frame's recursion overlap the next frame's work.  Every frame is rendered in full.
+    F = max(1, args.frames_in_flight)
+    streams = [torch.cuda.Stream() for _ in range(F)]
+    wss = [ws] + [Workspace.for_camera(cam, gs.num_lights) for _ in range(F - 1)]
+    outs_f = [out] + [alloc_outputs(cam, gs.num_lights, dev) for _ in range(F - 1)]
+
+    def run_frames(n, nstreams, timer=None, per_frame=None):
+        """Device milliseconds for n frames over the first nstreams streams (events bracket the run)."""
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(streams[0])
+        for st in streams[1:nstreams]:
+            st.wait_event(start)
+        for i in range(n):
+            k = i % nstreams
+            if per_frame is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e0.record(streams[k])
+            render_stereo(gs, cam, workspace=wss[k], outputs=outs_f[k], stream=streams[k], timer=timer)
+            if per_frame is not None:
+                e1 = torch.cuda.Event(enable_timing=True)
+                e1.record(streams[k])
+                per_frame.append((e0, e1))
+        for st in streams[1:nstreams]:
+            ev = torch.cuda.Event()
+            ev.record(st)
+            streams[0].wait_event(ev)
+        stop.record(streams[0])
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop)
+
+    run_frames(args.warmup, F)
     log(f"[bench] warmup done ({args.warmup} frames)")
+    single_ms = run_frames(args.steps, 1) / args.steps  # one stream, no timer: frames back to back
+    log(f"[bench] one frame in flight: {single_ms:.3f} ms/frame")
 
     timer = Timer()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     frame_ms = []
-    torch.cuda.synchronize()
     t_wall = time.perf_counter()
-    start.record()
-    for _ in range(args.steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        render_stereo(gs, cam, workspace=ws, outputs=out, timer=timer.handle)
-        e1.record()
-        frame_ms.append((e0, e1))
-    stop.record()
-    torch.cuda.synchronize()
+    total_ms = run_frames(args.steps, F, timer=timer.handle, per_frame=frame_ms)
     wall_s = time.perf_counter() - t_wall
-    total_ms = start.elapsed_time(stop)
     per_frame = [a.elapsed_time(b) for a, b in frame_ms]
     ms_per_step = total_ms / args.steps
     stages = timer.read()
-    log(f"[bench] timed {args.steps} frames: {ms_per_step:.3f} ms/frame (median {np.median(per_frame):.3f}), "
-        f"wall {wall_s:.2f} s")
+    log(f"[bench] timed {args.steps} frames, {F} in flight: {ms_per_step:.3f} ms/frame "
+        f"(frame latency median {np.median(per_frame):.3f} ms), wall {wall_s:.2f} s")
     for k, (ms, n) in stages.items():
         if n:
             log(f"[bench]   {k:14s} {ms / args.steps:8.3f} ms/frame over {n // args.steps} launches/frame")
 
-    # end to end: render + pinned async readback on a side stream, double-buffered, for both
-    # readback modes (hipMemcpyAsync, and the narrow copy kernel writing through the pinned buffer)
+    # end to end: render + pinned async readback, each render stream with its own copy stream and
+    # two host buffers, for both readback modes (hipMemcpyAsync, and the narrow copy kernel writing
+    # through the pinned buffer)
     e2e = {}
     if not args.no_end_to_end:
-        outs = [alloc_outputs(cam, gs.num_lights, dev, host=True, counts=False) for _ in range(2)]
-        copy = torch.cuda.Stream()
+        outs = [alloc_outputs(cam, gs.num_lights, dev, host=True, counts=False) for _ in range(2 * F)]
+        copies = [torch.cuda.Stream() for _ in range(F)]
         e2e_frames = max(args.steps, 30)  # wall-clock timing: enough frames to average out host jitter
 
         def stream_frames(mode, n):
             done = []
             for i in range(n):
-                o = outs[i % 2]
-                if i >= 2:
-                    done[i - 2].synchronize()  # the host buffer of two frames ago has been consumed
-                render_stereo(gs, cam, workspace=ws, outputs=o, copy_stream=copy, readback_kernel=(mode == "kernel"))
+                k = i % F
+                o = outs[i % (2 * F)]
+                if i >= 2 * F:
+                    done[i - 2 * F].synchronize()  # the host buffer's previous frame has been consumed
+                render_stereo(gs, cam, workspace=wss[k], outputs=o, stream=streams[k], copy_stream=copies[k],
+                              readback_kernel=(mode == "kernel"))
                 ev = torch.cuda.Event()
-                ev.record(copy)
+                ev.record(copies[k])
                 done.append(ev)
-            copy.synchronize()
             torch.cuda.synchronize()
 
         for mode in ("memcpy", "kernel"):
-            stream_frames(mode, 3)  # warm-up: first use of the mode's copy path and the pinned pages
+            stream_frames(mode, 3 * F)  # warm-up: first use of the mode's copy path and the pinned pages
             t1 = time.perf_counter()
             stream_frames(mode, e2e_frames)
             e2e[mode] = (time.perf_counter() - t1) * 1e3 / e2e_frames
@@ -485,7 +513,9 @@ def main():
         "stereo_fps_end_to_end": (1e3 / e2e_best) if e2e_best else None,
         "ms_per_step_end_to_end": e2e_best,
         "ms_per_step_end_to_end_by_readback": e2e or None,
-        "ms_per_step_p50": float(np.median(per_frame)),
+        "frames_in_flight": F,
+        "ms_per_step_one_in_flight": single_ms,
+        "frame_latency_ms_p50": float(np.median(per_frame)),
         "rays_per_frame": rays,
         "ray_counts": {"primary": int(cnt[0]), "mirror": int(cnt[1]), "shadow": int(cnt[2])},
         "stage_ms_per_frame": {k: v[0] / args.steps for k, v in stages.items() if v[1]},

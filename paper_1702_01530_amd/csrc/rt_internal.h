@@ -95,7 +95,10 @@ struct DevItem {
 
 // Device-scope atomics on one address serialise; the traversal's work cursor is split into this
 // many counters, each serving an interleaved share of the batches.
-constexpr int kWorkCounters = 16;
+#ifndef SRT_WORK_COUNTERS
+#define SRT_WORK_COUNTERS 16
+#endif
+constexpr int kWorkCounters = SRT_WORK_COUNTERS;
 
 // Work counters inside the render workspace.
 struct Counters {
