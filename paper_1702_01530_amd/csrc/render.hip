@@ -40,6 +40,13 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kStackLds = SRT_STACK_LDS;       // traversal stack entries per lane kept in LDS (power of two)
 constexpr int kStackGlobal = kStackMax - kStackLds;  // older entries spill to the workspace
 constexpr int kMaxTraceBlocks = 2048;
+// Shading blocks are large: queue slots are reserved with one device-scope atomic per block
+// iteration and queue, and atomics on one address serialise.
+#ifndef SRT_SHADE_BLOCK
+#define SRT_SHADE_BLOCK 512
+#endif
+constexpr int kShadeBlock = SRT_SHADE_BLOCK;
+constexpr int kShadeWaves = kShadeBlock / 64;
 static_assert((kStackLds & (kStackLds - 1)) == 0, "LDS stack size must be a power of two");
 
 // ---------------------------------------------------------------------------------------------
@@ -587,15 +594,15 @@ __device__ inline int32_t out_id(const DevScene& sc, int key) {
 // ---------------------------------------------------------------------------------------------
 
 template <bool PATH_IDS, bool MULTI>
-__global__ __launch_bounds__(kBlock) void k_shade(KArgs a, int depth) {
-  __shared__ uint32_t wcnt[kWaves][RT_MAX_LIGHTS + 1];
+__global__ __launch_bounds__(kShadeBlock) void k_shade(KArgs a, int depth) {
+  __shared__ uint32_t wcnt[kShadeWaves][RT_MAX_LIGHTS + 1];
   __shared__ uint32_t bbase[RT_MAX_LIGHTS + 1];
   const int lane = lane_id(), wave = threadIdx.x >> 6;
   const int q = depth & 1, nq = (depth + 1) & 1;
   const uint32_t total = depth == 0 ? uint32_t(a.path_count) : a.ctr->refl_count[depth];
   const int LS = a.lstride;
   uint32_t n_primary = 0;
-  for (uint32_t base = blockIdx.x * kBlock; base < total; base += gridDim.x * kBlock) {  // block-uniform loop
+  for (uint32_t base = blockIdx.x * kShadeBlock; base < total; base += gridDim.x * kShadeBlock) {  // block-uniform loop
     const uint32_t e = base + threadIdx.x;
     bool active = e < total;
     float4 ro = make_float4(0.f, 0.f, 0.f, __int_as_float(-1)), rd = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -684,7 +691,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(KArgs a, int depth) {
     if (threadIdx.x <= uint32_t(LS)) {
       const int l = threadIdx.x;
       uint32_t run = 0;
-      for (int w = 0; w < kWaves; ++w) {
+      for (int w = 0; w < kShadeWaves; ++w) {
         const uint32_t c = wcnt[w][l];
         wcnt[w][l] = run;
         run += c;
@@ -800,9 +807,10 @@ __global__ __launch_bounds__(kBlock) void k_copy_to_host4(const uint32_t* __rest
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <typename K>
-hipError_t launch(K kernel, unsigned grid, const KArgs& a, int depth, hipStream_t s, TimerImpl* timer, int stage) {
+hipError_t launch(K kernel, unsigned grid, const KArgs& a, int depth, hipStream_t s, TimerImpl* timer, int stage,
+                  int block = kBlock) {
   if (timer) timer_begin(timer, stage, s);
-  kernel<<<grid, kBlock, 0, s>>>(a, depth);
+  kernel<<<grid, block, 0, s>>>(a, depth);
   hipError_t e = hipGetLastError();
   if (timer) timer_end(timer, stage, s);
   return e;
@@ -907,6 +915,8 @@ hipError_t render_chunk(const RenderArgs& ra, hipStream_t s, TimerImpl* timer) {
   const unsigned gtrace = unsigned(p.grid_trace);
   const unsigned gstream =
       unsigned(std::max<int64_t>(1, std::min<int64_t>((ra.path_count + kBlock - 1) / kBlock, ra.stream_blocks)));
+  const unsigned gshade = unsigned(std::max<int64_t>(
+      1, std::min<int64_t>((ra.path_count + kShadeBlock - 1) / kShadeBlock, ra.stream_blocks * kBlock / kShadeBlock)));
   hipError_t e;
   if (timer) timer_begin(timer, RT_STAGE_SETUP, s);
   k_reset<<<1, 256, 0, s>>>(a.ctr);
@@ -924,11 +934,11 @@ hipError_t render_chunk(const RenderArgs& ra, hipStream_t s, TimerImpl* timer) {
     if (e != hipSuccess) return e;
     if (d <= D) {
       if (multi)
-        e = ids ? launch(k_shade<true, true>, gstream, a, d, s, timer, RT_STAGE_SHADE)
-                : launch(k_shade<false, true>, gstream, a, d, s, timer, RT_STAGE_SHADE);
+        e = ids ? launch(k_shade<true, true>, gshade, a, d, s, timer, RT_STAGE_SHADE, kShadeBlock)
+                : launch(k_shade<false, true>, gshade, a, d, s, timer, RT_STAGE_SHADE, kShadeBlock);
       else
-        e = ids ? launch(k_shade<true, false>, gstream, a, d, s, timer, RT_STAGE_SHADE)
-                : launch(k_shade<false, false>, gstream, a, d, s, timer, RT_STAGE_SHADE);
+        e = ids ? launch(k_shade<true, false>, gshade, a, d, s, timer, RT_STAGE_SHADE, kShadeBlock)
+                : launch(k_shade<false, false>, gshade, a, d, s, timer, RT_STAGE_SHADE, kShadeBlock);
       if (e != hipSuccess) return e;
     }
     if (d >= 1) {
