@@ -461,3 +461,33 @@ def test_terrain3m_1080p_sampled(torch_cuda, terrain_3m):
     scene, cam = terrain_3m
     samples = sg.sample_paths(cam, 384, seed=31)
     check_parity(torch_cuda, scene, cam, samples=samples)
+
+
+def test_terrain3m_4k_sampled(torch_cuda, terrain_3m):
+    """The 3.4M-triangle scene at 3840x2160 per eye (the roofline configuration), sampled paths."""
+    scene, cam = terrain_3m
+    cam = cam.resized(3840, 2160)
+    samples = sg.sample_paths(cam, 256, seed=41)
+    check_parity(torch_cuda, scene, cam, samples=samples)
+
+
+def test_frames_in_flight_equal_single(torch_cuda, terrain_3m):
+    """The benchmark's launch configuration: two frames rendered concurrently on their own streams and
+    workspaces give the same bytes as one frame rendered alone."""
+    torch = torch_cuda
+    from paper_1702_01530_amd.stereo import GpuScene, Workspace, alloc_outputs, render_stereo
+    scene, cam = terrain_3m
+    gs = GpuScene(scene)
+    ref = render_stereo(gs, cam, workspace=Workspace.for_camera(cam, gs.num_lights))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    wss = [Workspace.for_camera(cam, gs.num_lights) for _ in range(2)]
+    outs = [alloc_outputs(cam, gs.num_lights, torch.device("cuda")) for _ in range(2)]
+    for rep in range(2):
+        for k in range(2):
+            render_stereo(gs, cam, workspace=wss[k], outputs=outs[k], stream=streams[k])
+        torch.cuda.synchronize()
+        for k in range(2):
+            for name in ("radiance", "hit_t", "hit_prim"):
+                assert torch.equal(outs[k][name], ref[name]), (rep, k, name)
+    gs.close()
