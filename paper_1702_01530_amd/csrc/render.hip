@@ -731,9 +731,15 @@ __global__ __launch_bounds__(kShadeBlock) void k_shade(KArgs a, int depth) {
     }
     __syncthreads();  // wcnt / bbase are reused by the next iteration
   }
-  if (depth == 0) {
+  if (depth == 0) {  // one atomic per block: device-scope atomics on one address serialise
     for (int off = 32; off > 0; off >>= 1) n_primary += __shfl_xor(n_primary, off);
-    if (lane == 0 && n_primary) atomicAdd(&a.ctr->primary, n_primary);
+    if (lane == 0) wcnt[wave][0] = n_primary;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t sum = 0;
+      for (int w = 0; w < kShadeWaves; ++w) sum += wcnt[w][0];
+      if (sum) atomicAdd(&a.ctr->primary, sum);
+    }
   }
 }
 
