@@ -330,6 +330,47 @@ def bench_paper_shapes(args):
     print(json.dumps({"metric": "paper experiment shapes", "config": {"workload": "paper_shapes"}, **res}), flush=True)
 
 
+def bench_builders(args):
+    """The two tree builders on the benchmark scene: build time, node visits per ray, frame time."""
+    import numpy as np
+    import torch
+    from paper_1702_01530_amd.stereo import GpuScene, Workspace, alloc_outputs, render_stereo
+    scene, cam = workload("terrain3.4M_1080p")
+    dev = torch.device("cuda")
+    res = {"workload": "terrain3.4M_1080p", "builders": {}}
+    for accel in ("lbvh", "lbvh_karras"):
+        GpuScene(scene, accel=accel).close()  # first build pays one-time costs (code loading, allocation)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gs = GpuScene(scene, accel=accel)
+        torch.cuda.synchronize()
+        build_ms = (time.perf_counter() - t0) * 1e3
+        ws = Workspace.for_camera(cam, gs.num_lights)
+        out = alloc_outputs(cam, gs.num_lights, dev)
+        render_stereo(gs, cam, count_work=True, workspace=ws, outputs=out)
+        torch.cuda.synchronize()
+        c = out["ray_counts"].cpu().numpy().astype(np.int64)
+        for _ in range(3):
+            render_stereo(gs, cam, workspace=ws, outputs=out)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(args.steps):
+            render_stereo(gs, cam, workspace=ws, outputs=out)
+        stop.record()
+        torch.cuda.synchronize()
+        info = gs.info()
+        r = {"build_ms": build_ms, "ms_per_frame_one_in_flight": start.elapsed_time(stop) / args.steps,
+             "closest_nodes_per_ray": float(c[3] / (c[0] + c[1])), "shadow_nodes_per_ray": float(c[5] / c[2]),
+             "closest_tris_per_ray": float(c[4] / (c[0] + c[1])), "shadow_tris_per_ray": float(c[6] / c[2]),
+             "bvh_depth": info["bvh_depth"], "nodes": info["num_nodes"]}
+        res["builders"][accel] = r
+        log(f"[builders] {accel}: build {build_ms:.1f} ms, {r['closest_nodes_per_ray']:.1f} / "
+            f"{r['shadow_nodes_per_ray']:.1f} nodes per closest / shadow ray, {r['ms_per_frame_one_in_flight']:.3f} ms/frame")
+        gs.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -374,6 +415,8 @@ def main():
     rt.lib()
     if args.workload == "paper_shapes":
         return bench_paper_shapes(args)
+    if args.workload == "builders":
+        return bench_builders(args)
     if args.workload == "serve":
         return bench_serve(args)
     if args.workload == "batch64":

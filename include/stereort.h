@@ -84,8 +84,11 @@ typedef struct {
 } rt_light;
 
 enum {
-  RT_ACCEL_LBVH = 0u, /* triangles through a linear BVH (default) */
-  RT_ACCEL_NONE = 1u  /* brute force: every triangle is tested for every ray */
+  RT_ACCEL_LBVH = 0u,        /* triangles through a BVH built from the Morton order by locally-ordered
+                                clustering (default) */
+  RT_ACCEL_NONE = 1u,        /* brute force: every triangle is tested for every ray */
+  RT_ACCEL_LBVH_KARRAS = 2u  /* the same BVH layout with the binary tree from Karras (2012) emission over
+                                the Morton order and a bottom-up box refit */
 };
 
 typedef struct {

@@ -122,7 +122,8 @@ rt_status validate_desc(const rt_scene_desc* d) {
     return fail(RT_ERR_INVALID_ARGUMENT, "num_materials %d out of range [1, %d]", d->num_materials, RT_MAX_MATERIALS);
   if (d->num_lights < 0 || d->num_lights > RT_MAX_LIGHTS)
     return fail(RT_ERR_INVALID_ARGUMENT, "num_lights %d out of range [0, %d]", d->num_lights, RT_MAX_LIGHTS);
-  if (d->flags & ~uint32_t(RT_ACCEL_NONE)) return fail(RT_ERR_INVALID_ARGUMENT, "unknown scene flags 0x%x", d->flags);
+  if (d->flags != RT_ACCEL_LBVH && d->flags != RT_ACCEL_NONE && d->flags != RT_ACCEL_LBVH_KARRAS)
+    return fail(RT_ERR_INVALID_ARGUMENT, "unknown scene flags 0x%x", d->flags);
   if (!finite3(d->ambient) || !finite3(d->background))
     return fail(RT_ERR_INVALID_ARGUMENT, "ambient and background must be finite");
   return RT_OK;
@@ -416,7 +417,7 @@ rt_status rt_scene_storage_size(const rt_scene_desc* desc, size_t* storage_bytes
   if (s != RT_OK) return s;
   if (!storage_bytes || !scratch_bytes) return fail(RT_ERR_INVALID_ARGUMENT, "size outputs are NULL");
   srt::BuildPlan p = srt::plan_build(desc->num_triangles, desc->num_spheres, desc->num_planes, desc->num_materials,
-                                     desc->num_lights, desc->flags == RT_ACCEL_LBVH);
+                                     desc->num_lights, desc->flags != RT_ACCEL_NONE, desc->flags == RT_ACCEL_LBVH);
   *storage_bytes = p.storage_bytes;
   *scratch_bytes = p.scratch_bytes;
   return ok();
@@ -443,7 +444,7 @@ rt_status rt_scene_build(const rt_scene_desc* desc, void* storage, size_t storag
     if (!finite3(desc->lights[i].position) || !finite3(desc->lights[i].intensity))
       return fail(RT_ERR_INVALID_ARGUMENT, "light %d is not finite", i);
   srt::BuildPlan plan = srt::plan_build(desc->num_triangles, desc->num_spheres, desc->num_planes, desc->num_materials,
-                                        desc->num_lights, desc->flags == RT_ACCEL_LBVH);
+                                        desc->num_lights, desc->flags != RT_ACCEL_NONE, desc->flags == RT_ACCEL_LBVH);
   if (!storage || !scratch) return fail(RT_ERR_INVALID_ARGUMENT, "storage and scratch must be device pointers");
   if (!aligned256(storage) || !aligned256(scratch))
     return fail(RT_ERR_INVALID_ARGUMENT, "storage and scratch must be 256-byte aligned");

@@ -8,8 +8,8 @@
 //   4. stable LSD radix sort of (code, triangle id), 8 passes of 8 bits;
 //   5. binary tree over the sorted leaves: by default locally-ordered clustering
 //      (PLOC: neighbours in the Morton order merge by smallest surface area, so
-//      node boxes come with the merges); with SRT_PLOC=0, Karras (2012) emission
-//      (split at the highest differing bit; equal codes split by index) followed by
+//      node boxes come with the merges); with RT_ACCEL_LBVH_KARRAS, Karras (2012)
+//      emission (split at the highest differing bit; equal codes split by index) and
 //   6. a bottom-up box refit (an atomic arrival counter per node, the second
 //      child to arrive unions both boxes and climbs on);
 //   7. top-down collapse into a 4-wide tree, one level per launch, with the
@@ -19,9 +19,6 @@
 
 #include <hip/hip_runtime.h>
 
-#ifndef SRT_PLOC
-#define SRT_PLOC 1
-#endif
 
 #include <algorithm>
 #include <cmath>
@@ -790,10 +787,11 @@ hipError_t scan_exclusive(uint32_t* data, int64_t m, uint32_t* total_out, uint32
   return hipGetLastError();
 }
 
-BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool bvh) {
+BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool bvh, bool ploc) {
   BuildPlan p{};
   p.T = T;
   p.bvh = bvh && T >= 2;
+  p.ploc = ploc;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -827,25 +825,27 @@ BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool
     p.ids1_off = take(size_t(T) * 4);
     p.hist_off = take(size_t(p.num_sort_blocks) * kRadix * 4);
     p.children_off = take(size_t(T) * 8);
-    p.range_off = take(size_t(T) * 8);
-    p.parent_off = take(size_t(2 * T) * 4);
-    p.flags_off = take(size_t(T) * 4);
     p.nodebox_off = take(size_t(T) * 32);
+    if (!ploc) {
+      p.range_off = take(size_t(T) * 8);
+      p.parent_off = take(size_t(2 * T) * 4);
+      p.flags_off = take(size_t(T) * 4);
+    }
     p.frontier_off[0] = take(size_t(T) * 8);
     p.frontier_off[1] = take(size_t(T) * 8);
     p.sel_off = take(size_t(T) * 16);
     p.nint_off = take(size_t(T + 1) * 4);
     p.scan_tmp_off = take(size_t(scan_tmp_entries(std::max<int64_t>(T + 1, p.num_sort_blocks * kRadix))) * 4);
-#if SRT_PLOC
-    for (int k = 0; k < 2; ++k) {
-      p.ploc_lo_off[k] = take(size_t(T) * 16);
-      p.ploc_hi_off[k] = take(size_t(T) * 16);
-      p.ploc_ref_off[k] = take(size_t(T) * 4);
+    if (ploc) {
+      for (int k = 0; k < 2; ++k) {
+        p.ploc_lo_off[k] = take(size_t(T) * 16);
+        p.ploc_hi_off[k] = take(size_t(T) * 16);
+        p.ploc_ref_off[k] = take(size_t(T) * 4);
+      }
+      p.ploc_nn_off = take(size_t(T) * 4);
+      p.ploc_keep_off = take(size_t(T + 1) * 4);
+      p.ploc_merge_off = take(size_t(T + 1) * 4);
     }
-    p.ploc_nn_off = take(size_t(T) * 4);
-    p.ploc_keep_off = take(size_t(T + 1) * 4);
-    p.ploc_merge_off = take(size_t(T + 1) * 4);
-#endif
   }
   p.scratch_bytes = off;
   return p;
@@ -957,11 +957,7 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
       int32_t* parent = reinterpret_cast<int32_t*>(scratch + plan.parent_off);
       uint32_t* flags = reinterpret_cast<uint32_t*>(scratch + plan.flags_off);
       float4* nodebox = reinterpret_cast<float4*>(scratch + plan.nodebox_off);
-#if SRT_PLOC
-      (void)range;
-      (void)parent;
-      (void)flags;
-      {
+      if (plan.ploc) {
         float4* c_lo[2] = {reinterpret_cast<float4*>(scratch + plan.ploc_lo_off[0]),
                            reinterpret_cast<float4*>(scratch + plan.ploc_lo_off[1])};
         float4* c_hi[2] = {reinterpret_cast<float4*>(scratch + plan.ploc_hi_off[0]),
@@ -1010,22 +1006,21 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
           cur ^= 1;
         }
         if (next != 0) return hipErrorUnknown;  // T - 1 merges make a binary tree rooted at node 0
+        SRT_CHECK(hipMemcpyAsync(&bounds, partial, sizeof(bounds), hipMemcpyDeviceToHost, stream));
+        SRT_CHECK(hipStreamSynchronize(stream));
+      } else {
+        int32_t* dmax = reinterpret_cast<int32_t*>(status + 4);
+        k_karras<<<blocks_for(T - 1), kBlock, 0, stream>>>(k0, T, children, parent, range);
+        SRT_LAUNCH_CHECK();
+        k_fill<uint32_t><<<blocks_for(T - 1), kBlock, 0, stream>>>(flags, 0u, T - 1);
+        SRT_LAUNCH_CHECK();
+        k_refit<<<blocks_for(T), kBlock, 0, stream>>>(children, parent, lo, hi, i0, nodebox, flags, T, dmax, status);
+        SRT_LAUNCH_CHECK();
+        // read back the scene bounds for the padding
+        SRT_CHECK(hipMemcpyAsync(&bounds, partial, sizeof(bounds), hipMemcpyDeviceToHost, stream));
+        SRT_CHECK(hipMemcpyAsync(&depth, dmax, sizeof(depth), hipMemcpyDeviceToHost, stream));
+        SRT_CHECK(hipStreamSynchronize(stream));
       }
-      SRT_CHECK(hipMemcpyAsync(&bounds, partial, sizeof(bounds), hipMemcpyDeviceToHost, stream));
-      SRT_CHECK(hipStreamSynchronize(stream));
-#else
-      int32_t* dmax = reinterpret_cast<int32_t*>(status + 4);
-      k_karras<<<blocks_for(T - 1), kBlock, 0, stream>>>(k0, T, children, parent, range);
-      SRT_LAUNCH_CHECK();
-      k_fill<uint32_t><<<blocks_for(T - 1), kBlock, 0, stream>>>(flags, 0u, T - 1);
-      SRT_LAUNCH_CHECK();
-      k_refit<<<blocks_for(T), kBlock, 0, stream>>>(children, parent, lo, hi, i0, nodebox, flags, T, dmax, status);
-      SRT_LAUNCH_CHECK();
-      // read back the scene bounds for the padding
-      SRT_CHECK(hipMemcpyAsync(&bounds, partial, sizeof(bounds), hipMemcpyDeviceToHost, stream));
-      SRT_CHECK(hipMemcpyAsync(&depth, dmax, sizeof(depth), hipMemcpyDeviceToHost, stream));
-      SRT_CHECK(hipStreamSynchronize(stream));
-#endif
       float coord_max = 0.f;
       for (int a = 0; a < 3; ++a)
         coord_max = std::max(coord_max, std::max(std::fabs(bounds.blo[a]), std::fabs(bounds.bhi[a])));

@@ -133,9 +133,11 @@ struct BuildPlan {
   size_t scratch_bytes;
   int64_t num_blocks_prep, num_sort_blocks;
   bool bvh;
+  bool ploc;
 };
 
-BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool bvh);
+// bvh: build a tree over the triangles; ploc: its binary tree by clustering (else Karras emission + refit)
+BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool bvh, bool ploc);
 int leaf_size();  // largest number of triangles the build puts in one leaf (1..kLeafMaxTris)
 
 struct BuildResult {

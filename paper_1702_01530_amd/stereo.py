@@ -35,9 +35,13 @@ class GpuScene:
     triangles [T,3,3], tri_material [T], spheres [S,4], sphere_material [S], planes [P,4],
     plane_material [P], materials [M,10], lights [L,6], ambient [3], background [3]."""
 
+    ACCEL = {"lbvh": rt.RT_ACCEL_LBVH, "lbvh_karras": rt.RT_ACCEL_LBVH_KARRAS, "none": rt.RT_ACCEL_NONE}
+
     def __init__(self, scene, accel: str = "lbvh", device=None, stream=None):
-        if accel not in ("lbvh", "none"):
-            raise ValueError("accel must be 'lbvh' or 'none'")
+        """accel: "lbvh" (tree by clustering over the Morton order), "lbvh_karras" (Karras emission + refit)
+        or "none" (brute force)."""
+        if accel not in self.ACCEL:
+            raise ValueError(f"accel must be one of {sorted(self.ACCEL)}")
         self.device = torch.device(device or "cuda")
         tri = _dev(scene.triangles, np.float32, self.device)
         # material indices are uint32 in the ABI; int32 tensors carry the same bits for values < 2^31
@@ -61,7 +65,7 @@ class GpuScene:
         d.lights = C.cast(self._lights, C.POINTER(rt.rt_light))
         d.ambient = rt._f3(scene.ambient)
         d.background = rt._f3(scene.background)
-        d.flags = rt.RT_ACCEL_LBVH if accel == "lbvh" else rt.RT_ACCEL_NONE
+        d.flags = self.ACCEL[accel]
         self.desc = d
         storage, scratch = rt.rt_scene_storage_size(d)
         self._storage, sptr = aligned_buffer(storage, self.device)

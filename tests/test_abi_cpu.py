@@ -42,6 +42,7 @@ def test_storage_size_queries():
     ("num_materials", 0, "num_materials"),
     ("num_lights", 9, "num_lights"),
     ("flags", 8, "flags"),
+    ("flags", 3, "flags"),
 ])
 def test_descriptor_validation(field, value, needle):
     d = _desc()
@@ -50,6 +51,17 @@ def test_descriptor_validation(field, value, needle):
         rt.rt_scene_storage_size(d)
     assert ei.value.status == rt.RT_ERR_INVALID_ARGUMENT
     assert needle in rt.last_error()
+
+
+def test_tree_builders_plan_their_own_scratch():
+    """Both tree builders are accepted; clustering needs more scratch than emission + refit, no more storage."""
+    sizes = {}
+    for flags in (rt.RT_ACCEL_LBVH, rt.RT_ACCEL_LBVH_KARRAS, rt.RT_ACCEL_NONE):
+        d = _desc(T=100000)
+        d.flags = flags
+        sizes[flags] = rt.rt_scene_storage_size(d)
+    assert sizes[rt.RT_ACCEL_LBVH][0] == sizes[rt.RT_ACCEL_LBVH_KARRAS][0] > sizes[rt.RT_ACCEL_NONE][0]
+    assert sizes[rt.RT_ACCEL_LBVH][1] > sizes[rt.RT_ACCEL_LBVH_KARRAS][1] > sizes[rt.RT_ACCEL_NONE][1]
 
 
 def test_build_rejects_bad_pointers_before_device_use():

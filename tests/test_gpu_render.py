@@ -64,17 +64,18 @@ def test_paper5_full_frame_lbvh_and_brute(torch_cuda):
         assert np.array_equal(gl[k], gb[k]), k
 
 
-@pytest.mark.parametrize("grid,spheres,level,lights,depth,size", [
-    (24, 4, 1, 2, 3, (96, 64)),
-    (40, 6, 2, 4, 4, (77, 45)),   # ragged tiles on both axes
+@pytest.mark.parametrize("grid,spheres,level,lights,depth,size,accel", [
+    (24, 4, 1, 2, 3, (96, 64), "lbvh"),
+    (40, 6, 2, 4, 4, (77, 45), "lbvh"),   # ragged tiles on both axes
+    (40, 6, 2, 4, 4, (77, 45), "lbvh_karras"),
 ])
-def test_small_terrain_full_frame(torch_cuda, grid, spheres, level, lights, depth, size):
+def test_small_terrain_full_frame(torch_cuda, grid, spheres, level, lights, depth, size, accel):
     scene, cam = sg.make_small_terrain(seed=11 + grid, grid=grid, n_spheres=spheres, level=level, lights=lights,
                                        depth=depth)
     cam = cam.resized(*size)
-    g, orc, res = check_parity(torch_cuda, scene, cam)
-    # the LBVH path and the brute-force path agree bitwise
-    gs, ob = render(torch_cuda, scene, cam, brute_force=True)
+    g, orc, res = check_parity(torch_cuda, scene, cam, accel=accel)
+    # the tree path and the brute-force path agree bitwise
+    gs, ob = render(torch_cuda, scene, cam, accel=accel, brute_force=True)
     b = gpu_flat(ob)
     for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state"):
         assert np.array_equal(g[k], b[k]), k
@@ -386,13 +387,14 @@ def _decode_children(rec: np.ndarray):
     return p[:, None] + qlo * step[:, None], p[:, None] + qhi * step[:, None], refs, valid
 
 
-def test_bvh_structure(torch_cuda):
+@pytest.mark.parametrize("accel", ["lbvh", "lbvh_karras"])
+def test_bvh_structure(torch_cuda, accel):
     """Reads the built tree back and walks it: every node is reached once, every triangle is in exactly
     one leaf, and every child's box (as the traversal sees it) contains the triangles under it."""
     import torch
     from paper_1702_01530_amd.stereo import GpuScene
     scene, _ = sg.make_small_terrain(seed=3, grid=48, n_spheres=8, level=2)
-    gs = GpuScene(scene)
+    gs = GpuScene(scene, accel=accel)
     info = gs.info()
     T = scene.num_triangles
     n_nodes = info["num_nodes"]
@@ -450,10 +452,11 @@ def terrain_3m():
     return sg.make_terrain_3m()
 
 
-def test_terrain212k_1080p_sampled(torch_cuda, terrain_212k):
+@pytest.mark.parametrize("accel", ["lbvh", "lbvh_karras"])
+def test_terrain212k_1080p_sampled(torch_cuda, terrain_212k, accel):
     scene, cam = terrain_212k
     samples = sg.sample_paths(cam, 1024, seed=21)
-    check_parity(torch_cuda, scene, cam, samples=samples)
+    check_parity(torch_cuda, scene, cam, samples=samples, accel=accel)
 
 
 def test_terrain3m_1080p_sampled(torch_cuda, terrain_3m):
