@@ -466,18 +466,19 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
   // refilling single lanes stalls the wave on every refill).  Device-scope atomics on one address
   // serialise, so: wave w's first batch is batch w, with no atomic (a launch whose work fits in
   // the first round takes none); later batches b = nwaves + c + K k come from counter c = w mod K
-  // of K interleaved counters, so K atomics proceed at once.
+  // of K = min(kWorkCounters, nwaves) interleaved counters, so K atomics proceed at once.
   const uint32_t nwaves = gridDim.x * uint32_t(kWaves);
   const uint32_t wid = blockIdx.x * uint32_t(kWaves) + uint32_t(threadIdx.x >> 6);
   const uint32_t nbatches = total / 64u;  // total is a multiple of 64
-  const uint32_t home = wid % uint32_t(kWorkCounters);
+  const uint32_t ncounters = nwaves < uint32_t(kWorkCounters) ? nwaves : uint32_t(kWorkCounters);  // each served
+  const uint32_t home = wid % ncounters;
   uint32_t batch = wid;
   for (bool first = true;; first = false) {
     if (!first) {
       if (nwaves + home >= nbatches) break;  // no batch left for this counter
       uint32_t k = 0;
       if (lane == 0) k = atomicAdd(&a.ctr->trace_work[depth][home][0], 1u);
-      batch = nwaves + home + uint32_t(kWorkCounters) * __shfl(k, 0);
+      batch = nwaves + home + ncounters * __shfl(k, 0);
     }
     if (batch >= nbatches) break;
     const uint32_t base = batch * 64u;

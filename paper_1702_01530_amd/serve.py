@@ -220,12 +220,19 @@ class GpuRenderer(Renderer):
         self.path_ids = path_ids
         self._pinned = collections.defaultdict(list)  # shape -> free pinned buffers
 
-    def output_bytes(self, cam) -> int:
+    def output_bytes(self, cam, num_lights: int = 0) -> int:
+        """Device bytes of one request's outputs: radiance, hit t and id per pixel of both eyes, and the
+        ray-tree signature (path ids, shadow states) when it is recorded."""
         n = 2 * int(cam.width) * int(cam.height)
-        return n * (12 + 4 + 4)
+        per_pixel = 12 + 4 + 4
+        if self.path_ids:
+            d1 = int(cam.max_depth) + 1
+            per_pixel += 4 * d1 + d1 * max(int(num_lights), 1)
+        return n * per_pixel
 
     def bytes_needed(self, req: Request) -> int:
-        return self.output_bytes(req.camera)
+        gs = self.scenes.get(req.scene_id)
+        return self.output_bytes(req.camera, gs.num_lights if gs is not None else 0)
 
     def paths(self, req: Request) -> int:
         tiles = -(-int(req.camera.width) // 8) * -(-int(req.camera.height) // 8)
