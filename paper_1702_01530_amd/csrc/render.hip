@@ -48,6 +48,14 @@ constexpr int kMaxTraceBlocks = 2048;
 constexpr int kShadeBlock = SRT_SHADE_BLOCK;
 constexpr int kShadeWaves = kShadeBlock / 64;
 static_assert((kStackLds & (kStackLds - 1)) == 0, "LDS stack size must be a power of two");
+// The builder emits the 4-wide tree level by level, so nodes 0 .. kLdsNodes-1 are its top levels,
+// which every ray crosses.  A single-scene traversal block copies them into LDS once per launch and
+// reads them from there, off the vector-memory path.  85 nodes are levels 0-3; a deeper copy
+// loses more to waves whose lanes split between LDS and global reads than it saves.
+#ifndef SRT_LDS_NODES
+#define SRT_LDS_NODES 85
+#endif
+constexpr int kLdsNodes = kQuantNodes ? SRT_LDS_NODES : 0;
 
 // ---------------------------------------------------------------------------------------------
 // Small vector helpers
@@ -220,14 +228,42 @@ __device__ inline float slab(float lox, float hix, float loy, float hiy, float l
 
 // Entry distances of the four children of BVH4 node `node` (+inf where the ray misses the child's
 // box inside [tmin, tmax]) and their references.
-__device__ __attribute__((always_inline)) inline void node4_children(const float4* __restrict__ nodes, int node,
+// Reads node `node` of the LDS array `lnodes`.  Written as LDS instructions because the compiler
+// merges two plain reads of the same shape from LDS and global memory into one flat read, which
+// takes the vector-memory path for every lane.
+__device__ __attribute__((always_inline)) inline void lds_read_node(const float4* lnodes, int node, float4& a,
+                                                                    float4& b, float4& c, float4& d) {
+  typedef __attribute__((address_space(3))) const float4 lds_float4;
+  const uint32_t addr = uint32_t(uintptr_t((const lds_float4*)lnodes)) + uint32_t(node) * 64u;
+  asm volatile(
+      "ds_read_b128 %0, %4\n\t"
+      "ds_read_b128 %1, %4 offset:16\n\t"
+      "ds_read_b128 %2, %4 offset:32\n\t"
+      "ds_read_b128 %3, %4 offset:48\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(d)
+      : "v"(addr)
+      : "memory");
+}
+
+// Nodes below `kc` are read from the LDS copy `lnodes` of the top of the tree.
+__device__ __attribute__((always_inline)) inline void node4_children(const float4* __restrict__ nodes,
+                                                                     const float4* lnodes, int kc, int node,
                                                                      float3 inv, float3 oi, float tmin, float tmax,
                                                                      float (&t)[4], int (&r)[4]) {
 #if SRT_QNODE
   // Slab planes of child k on axis a are p_a + q s_a, i.e. t = q (s_a / d_a) + (p_a - o_a) / d_a; the
   // near and far planes of an axis are picked once per node from the ray's direction sign.
-  const float4* n = nodes + 4 * node;
-  const float4 n0 = n[0], n1 = n[1], n2 = n[2], n3 = n[3];
+  float4 n0, n1, n2, n3;
+  if (node < kc) {
+    lds_read_node(lnodes, node, n0, n1, n2, n3);
+  } else {
+    const float4* n = nodes + 4 * node;
+    n0 = n[0];
+    n1 = n[1];
+    n2 = n[2];
+    n3 = n[3];
+  }
   const float ax = n0.w * inv.x, ay = n3.z * inv.y, az = n3.w * inv.z;  // steps are powers of two: exact
   const float bx = fmaf(n0.x, inv.x, -oi.x), by = fmaf(n0.y, inv.y, -oi.y), bz = fmaf(n0.z, inv.z, -oi.z);
   const bool px = inv.x >= 0.f, py = inv.y >= 0.f, pz = inv.z >= 0.f;
@@ -342,8 +378,8 @@ struct Best {
 // Candidates are tested against next_up(best.t) in the closest-hit case so that an exact tie in t
 // reaches the (t, id) comparison, and boxes entered exactly at best.t are not culled.
 template <bool ANY, bool COUNT>
-__device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tmin, int exclude, bool brute,
-                                Best& best, Stack& st, uint32_t& nnodes, uint32_t& ntris) {
+__device__ inline void traverse(const DevScene& sc, const float4* lnodes, int kc, float3 o, float3 d, float tmin,
+                                int exclude, bool brute, Best& best, Stack& st, uint32_t& nnodes, uint32_t& ntris) {
   auto accept = [&](float t, int key, int id) -> bool {  // returns true when the traversal can stop
     if (key == exclude || !(t < INFINITY)) return false;
     if (ANY) {
@@ -396,7 +432,7 @@ __device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tm
       const float tmax = limit();
       float t[4];
       int r[4];
-      node4_children(sc.nodes, node, inv, oi, tmin, tmax, t, r);
+      node4_children(sc.nodes, lnodes, kc, node, inv, oi, tmin, tmax, t, r);
       sort4(t, r);
       if (t[0] < INFINITY) {
         node = r[0];
@@ -415,6 +451,7 @@ __device__ inline void traverse(const DevScene& sc, float3 o, float3 d, float tm
       }
       for (int k = 0; k < count; ++k) {
         const int r = first + k;
+        if (r == exclude) continue;  // the secondary ray's own primitive: not fetched
         int id;
         const float t = tri_t(sc.tris, r, o, d, tmin, limit(), &id);
         if (COUNT) ++ntris;
@@ -448,10 +485,17 @@ __device__ inline void add_work(Counters* ctr, int slot, uint32_t v) {
 template <bool COUNT, bool MULTI>
 __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int depth) {
   __shared__ uint32_t lstack[kStackLds * kBlock];
+  __shared__ float4 lnodes[kLdsNodes > 0 ? 4 * kLdsNodes : 1];
   const int lane = lane_id();
   const int gtid = blockIdx.x * kBlock + threadIdx.x;
   Stack st{&lstack[threadIdx.x], a.gstack + gtid, a.trace_threads, 0, false};
   const int LS = a.lstride;
+  int kc = 0;  // nodes held in lnodes (the same for the whole block)
+  if (!MULTI && kLdsNodes > 0 && a.one.sc.has_bvh && a.one.sc.T > 0 && !a.brute) {
+    kc = min(kLdsNodes, a.one.sc.num_nodes);
+    for (int i = threadIdx.x; i < 4 * kc; i += kBlock) lnodes[i] = a.one.sc.nodes[i];
+    __syncthreads();
+  }
   const bool closest = depth <= a.dmax;
   const bool shadows = depth >= 1;
   const int q = depth & 1;
@@ -513,8 +557,8 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
         if (valid) {
           const DevScene sc = item_ref<MULTI>(a, k).sc;
           Best b{INFINITY, -1, 0x7fffffff};
-          traverse<false, COUNT>(sc, o, d, depth == 0 ? 0.0f : kSecondaryTmin, exclude, a.brute != 0, b, st,
-                                 c_nodes, c_tris);
+          traverse<false, COUNT>(sc, lnodes, kc, o, d, depth == 0 ? 0.0f : kSecondaryTmin, exclude, a.brute != 0,
+                                 b, st, c_nodes, c_tris);
           a.hit[e] = make_float2(b.t, __int_as_float(b.key));
         }
       }
@@ -540,8 +584,8 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
         const float dist = sqrtf(dot(Lv, Lv));
         const float3 Ld = (1.0f / dist) * Lv;
         Best b{dist, -1, 0};
-        traverse<true, COUNT>(sc, P, Ld, kSecondaryTmin, __float_as_int(rec.w), a.brute != 0, b, st, s_nodes,
-                              s_tris);
+        traverse<true, COUNT>(sc, lnodes, kc, P, Ld, kSecondaryTmin, __float_as_int(rec.w), a.brute != 0, b, st,
+                              s_nodes, s_tris);
         a.vis[sq][size_t(owner) * LS + l] = b.key < 0 ? 1 : 0;
       }
     }
