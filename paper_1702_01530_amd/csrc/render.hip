@@ -421,8 +421,9 @@ __device__ inline void traverse(const DevScene& sc, const float4* lnodes, int kc
   // so the leaf step of a wave runs with every lane that reached a leaf in this iteration.
   int node = sc.root;
   st.sp = 0;
-  // A valid tree visits each node and leaf at most once; the cap only guards against a corrupt one.
-  for (int64_t guard = 2 * int64_t(sc.T) + 64; guard > 0; --guard) {
+  // A valid tree visits each node and leaf at most once; the cap only guards against a corrupt one
+  // (T <= 2^29, so it fits 32 bits).
+  for (int guard = 2 * sc.T + 64; guard > 0; --guard) {
     if (node >= 0) {
       if (node >= sc.num_nodes) {  // corrupt reference: stop this ray, never read out of bounds
         st.overflow = true;
@@ -482,6 +483,28 @@ __device__ inline void add_work(Counters* ctr, int slot, uint32_t v) {
 #define SRT_TRACE_ATTR
 #endif
 
+// The single render's camera, read from the kernel-argument segment where it is used: the compiler
+// would otherwise keep its FP64 constants in scalar registers across the traversal loop and spill.
+__device__ __attribute__((always_inline)) inline const DevCamera& single_camera() {
+  typedef __attribute__((address_space(4))) const char kchar;
+  typedef __attribute__((address_space(4))) const DevCamera kcamera;
+  const kchar* base = (const kchar*)__builtin_amdgcn_kernarg_segment_ptr();
+  const kcamera* c = reinterpret_cast<const kcamera*>(base + offsetof(KArgs, one) + offsetof(DevItem, cam));
+  asm volatile("" : "+s"(c));
+  return *(const DevCamera*)c;
+}
+
+// The kernel's arguments read afresh from the kernel-argument segment: the empty asm hides that the
+// pointer is loop-invariant, so fields used once per batch are loaded where they are used instead of
+// being kept in scalar registers across the traversal loop, where they would spill.  A kernel's
+// first argument starts the segment.
+__device__ __attribute__((always_inline)) inline const KArgs& kernel_args() {
+  typedef __attribute__((address_space(4))) const KArgs kargs_t;
+  const kargs_t* p = (const kargs_t*)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return *(const KArgs*)p;
+}
+
 template <bool COUNT, bool MULTI>
 __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int depth) {
   __shared__ uint32_t lstack[kStackLds * kBlock];
@@ -525,6 +548,7 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
       batch = nwaves + home + ncounters * __shfl(k, 0);
     }
     if (batch >= nbatches) break;
+    const KArgs& a = kernel_args();  // the same values as the parameter, see kernel_args
     const uint32_t base = batch * 64u;
     if (base < nc_pad) {
       // ---- closest-hit batch
@@ -538,10 +562,11 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
           const int64_t p = a.path_begin + e;
           k = item_of<MULTI>(a, p);
           const DevItem& it = item_ref<MULTI>(a, k);
+          const DevCamera& cam = MULTI ? it.cam : single_camera();
           int eye, x, y;
-          valid = path_pixel(it.cam, p - it.path_offset, &eye, &x, &y);
+          valid = path_pixel(cam, p - it.path_offset, &eye, &x, &y);
           if (valid) {
-            primary_ray(it.cam, eye, x, y, &o, &d);
+            primary_ray(cam, eye, x, y, &o, &d);
             a.ro[q][e] = make_float4(o.x, o.y, o.z, __int_as_float(int(e)));
             a.rd[q][e] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
           } else {
