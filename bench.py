@@ -291,7 +291,7 @@ def bench_paper_shapes(args):
     gs = GpuScene(big)
     saved = rt.rt_get_tuning()
     rows = []
-    for per_cu in (1, 2, 3, 4, 5, 6):
+    for per_cu in (1, 2, 3, 4, 5, 6, 7):
         rt.rt_set_tuning(per_cu, saved["stream_blocks"], saved["max_pass_paths"])
         t = Timer()
         ws = Workspace.for_camera(bcam, gs.num_lights)

@@ -29,7 +29,7 @@
 #define SRT_STACK_LDS 16
 #endif
 #ifndef SRT_TRACE_WAVES_PER_EU
-#define SRT_TRACE_WAVES_PER_EU 0
+#define SRT_TRACE_WAVES_PER_EU 7
 #endif
 
 namespace srt {
@@ -477,11 +477,11 @@ __device__ inline void add_work(Counters* ctr, int slot, uint32_t v) {
 // each range padded to a multiple of 64 so that every wave batch is one kind of ray.
 // ---------------------------------------------------------------------------------------------
 
-#if SRT_TRACE_WAVES_PER_EU > 0
-#define SRT_TRACE_ATTR __attribute__((amdgpu_waves_per_eu(SRT_TRACE_WAVES_PER_EU, SRT_TRACE_WAVES_PER_EU)))
-#else
-#define SRT_TRACE_ATTR
-#endif
+// Traversal occupancy: the single-scene kernel is held to kTraceWaves waves per SIMD (a budget of
+// 72 VGPRs, which it meets without spilling); the batch and instrumented kernels, which would spill,
+// are left free.
+constexpr int kTraceWaves = SRT_TRACE_WAVES_PER_EU;
+#define SRT_TRACE_ATTR __attribute__((amdgpu_waves_per_eu(COUNT || MULTI || kTraceWaves <= 0 ? 1 : kTraceWaves)))
 
 // The single render's camera, read from the kernel-argument segment where it is used: the compiler
 // would otherwise keep its FP64 constants in scalar registers across the traversal loop and spill.
