@@ -258,8 +258,10 @@ rt_status rt_batch_graph_destroy(rt_batch_graph graph);
 
 /* Launch tuning (process-wide).  Results are identical for every setting; only
  * speed changes.  trace_blocks_per_cu: persistent traversal workgroups per CU
- * (0 = as many as fit); stream_blocks: workgroups of the shading launches;
- * max_pass_paths: largest number of paths per pass (>= 4096). */
+ * (0 = as many as fit); stream_blocks: grid of the streaming launches, in units
+ * of 256 threads (the shading kernel's 512-thread blocks take half as many);
+ * max_pass_paths: largest number of paths per pass (>= 4096).  Defaults: 0, 8192,
+ * 2^25. */
 typedef struct {
   int32_t trace_blocks_per_cu;
   int32_t stream_blocks;

@@ -81,7 +81,7 @@ thread_local std::string g_error;
 
 // Launch tuning (process-wide): results never depend on it, only speed does.
 std::mutex g_tuning_mutex;
-rt_tuning g_tuning = {0, 2048, int64_t(1) << 25};
+rt_tuning g_tuning = {0, 8192, int64_t(1) << 25};
 
 rt_tuning current_tuning() {
   std::lock_guard<std::mutex> lock(g_tuning_mutex);

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "rt_internal.h"
@@ -118,6 +119,10 @@ struct KArgs {
   int32_t brute;
   int32_t trace_threads;  // threads in the persistent traversal grid (gstack stride)
 };
+// Kernels take KArgs by value as their first argument, so its bytes start the kernel-argument
+// segment (kernel_args reads them there).
+static_assert(std::is_trivially_copyable<KArgs>::value && std::is_standard_layout<KArgs>::value,
+              "KArgs must be plain data");
 
 // The item a path belongs to: binary search over the items' first path ids.
 template <bool MULTI>
@@ -483,17 +488,6 @@ __device__ inline void add_work(Counters* ctr, int slot, uint32_t v) {
 constexpr int kTraceWaves = SRT_TRACE_WAVES_PER_EU;
 #define SRT_TRACE_ATTR __attribute__((amdgpu_waves_per_eu(COUNT || MULTI || kTraceWaves <= 0 ? 1 : kTraceWaves)))
 
-// The single render's camera, read from the kernel-argument segment where it is used: the compiler
-// would otherwise keep its FP64 constants in scalar registers across the traversal loop and spill.
-__device__ __attribute__((always_inline)) inline const DevCamera& single_camera() {
-  typedef __attribute__((address_space(4))) const char kchar;
-  typedef __attribute__((address_space(4))) const DevCamera kcamera;
-  const kchar* base = (const kchar*)__builtin_amdgcn_kernarg_segment_ptr();
-  const kcamera* c = reinterpret_cast<const kcamera*>(base + offsetof(KArgs, one) + offsetof(DevItem, cam));
-  asm volatile("" : "+s"(c));
-  return *(const DevCamera*)c;
-}
-
 // The kernel's arguments read afresh from the kernel-argument segment: the empty asm hides that the
 // pointer is loop-invariant, so fields used once per batch are loaded where they are used instead of
 // being kept in scalar registers across the traversal loop, where they would spill.  A kernel's
@@ -562,7 +556,7 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
           const int64_t p = a.path_begin + e;
           k = item_of<MULTI>(a, p);
           const DevItem& it = item_ref<MULTI>(a, k);
-          const DevCamera& cam = MULTI ? it.cam : single_camera();
+          const DevCamera& cam = it.cam;
           int eye, x, y;
           valid = path_pixel(cam, p - it.path_offset, &eye, &x, &y);
           if (valid) {

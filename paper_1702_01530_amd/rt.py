@@ -232,7 +232,7 @@ def rt_get_tuning() -> dict:
     return {k: getattr(t, k) for k, _ in rt_tuning._fields_}
 
 
-def rt_set_tuning(trace_blocks_per_cu=0, stream_blocks=2048, max_pass_paths=1 << 25):
+def rt_set_tuning(trace_blocks_per_cu=0, stream_blocks=8192, max_pass_paths=1 << 25):
     t = rt_tuning(trace_blocks_per_cu, stream_blocks, max_pass_paths)
     check(lib().rt_set_tuning(C.byref(t)))
 
