@@ -14,7 +14,9 @@
 //      child to arrive unions both boxes and climbs on);
 //   7. top-down collapse into a 4-wide tree, one level per launch, with the
 //      children's boxes quantised to 8 bits on each node's own grid (64-byte
-//      nodes), and 48-byte triangle records in leaf order.
+//      nodes), and 48-byte triangle records in leaf order.  The clustering tree is
+//      cut where a bottom-up surface-area cost table says (one launch per
+//      clustering round); the Karras tree by the largest-area rule.
 // Every step is deterministic, so a scene always builds the same tree.
 
 #include <hip/hip_runtime.h>
@@ -24,6 +26,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <utility>
+#include <vector>
 
 #include "rt_internal.h"
 
@@ -577,10 +581,11 @@ __global__ __launch_bounds__(kBlock) void k_ploc_compact(PlocCompactArgs a) {
 
 // ---------------------------------------------------------------------------------------------
 // 7. Collapse into a 4-wide BVH, top-down one level at a time.  A BVH4 node takes a binary node's two
-// children and, while it has fewer than four, replaces its largest-area internal child by that
-// child's two children (keeping left-to-right order).  Internal children become the next level's
-// nodes; their indices come from a prefix sum, so the layout is deterministic and each level's
-// nodes are contiguous.
+// children and opens some of them into their own children (keeping left-to-right order) until it
+// holds up to four: where the cost table below says (clustering tree), or else by replacing the
+// largest-area internal child while fewer than four (Karras tree).  Internal children become the
+// next level's nodes; their indices come from a prefix sum, so the layout is deterministic and each
+// level's nodes are contiguous.
 // ---------------------------------------------------------------------------------------------
 
 constexpr int kWideEmpty = INT32_MIN;
@@ -599,11 +604,65 @@ struct WideArgs {
   float4* nodes;         // 8 float4 per BVH4 node
   int64_t level_base;    // BVH4 index of the next level's first node
   float pad;
+  const uint32_t* dp_choice;  // per binary node: the cost-optimal cut (nullptr: largest-area rule)
 };
 
 __device__ inline float half_area(float4 lo, float4 hi) {
   const float dx = hi.x - lo.x, dy = hi.y - lo.y, dz = hi.z - lo.z;
   return dx * dy + dy * dz + dz * dx;
+}
+
+#ifndef SRT_DP_TRI_COST
+#define SRT_DP_TRI_COST 0.5f
+#endif
+// Cost-optimal collapse (surface-area model): C(n, j) is the least expected cost of binary subtree
+// n when it may take j slots of its BVH4 parent.  C(n, 1) = A(n) + D_n(4) (n becomes a BVH4 node
+// whose four slots are shared by its two children), D_n(j) = min over k of C(a, k) + C(b, j - k),
+// and C(n, j) = min(C(n, 1), D_n(j)) for j > 1 (n kept whole, or opened across j slots).  A leaf
+// costs its area times the relative cost of a triangle test in every slot count.  Nodes of one
+// clustering round are computed together, rounds in the order they merged (children first).
+// Choice bits per node, for j = 2, 3, 4 at bit 3 (j - 2): the split k (2 bits) and whether opening wins.
+__device__ inline void dp_child_costs(int r, const float4* dp_cost, const float4* leaf_lo, const float4* leaf_hi,
+                                      const uint32_t* sorted_ids, float c_tri, float (&c)[4]) {
+  if (r < 0) {
+    const uint32_t id = sorted_ids[~r];
+    const float a = c_tri * half_area(leaf_lo[id], leaf_hi[id]);
+    c[0] = c[1] = c[2] = c[3] = a;
+  } else {
+    const float4 v = dp_cost[r];
+    c[0] = v.x, c[1] = v.y, c[2] = v.z, c[3] = v.w;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_wide_dp(const int2* __restrict__ children, const float4* nodebox,
+                                                    const float4* leaf_lo, const float4* leaf_hi,
+                                                    const uint32_t* sorted_ids, float4* dp_cost,
+                                                    uint32_t* dp_choice, int64_t first, int64_t count) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= count) return;
+  const int64_t n = first + i;
+  const int2 ch = children[n];
+  float ca[4], cb[4];
+  dp_child_costs(ch.x, dp_cost, leaf_lo, leaf_hi, sorted_ids, SRT_DP_TRI_COST, ca);
+  dp_child_costs(ch.y, dp_cost, leaf_lo, leaf_hi, sorted_ids, SRT_DP_TRI_COST, cb);
+  float D[5];
+  int K[5];
+  for (int j = 2; j <= 4; ++j) {
+    D[j] = INFINITY;
+    K[j] = 1;
+    for (int k = 1; k < j; ++k) {
+      const float c = ca[k - 1] + cb[j - k - 1];
+      if (c < D[j]) {
+        D[j] = c;
+        K[j] = k;
+      }
+    }
+  }
+  const float c1 = half_area(nodebox[2 * n], nodebox[2 * n + 1]) + D[4];
+  dp_cost[n] = make_float4(c1, fminf(c1, D[2]), fminf(c1, D[3]), fminf(c1, D[4]));
+  uint32_t choice = 0;
+  for (int j = 2; j <= 4; ++j) choice |= (uint32_t(K[j]) | (D[j] < c1 ? 4u : 0u)) << (3 * (j - 2));
+  dp_choice[n] = choice;
 }
 
 __global__ __launch_bounds__(kBlock) void k_wide_select(WideArgs a) {
@@ -612,7 +671,41 @@ __global__ __launch_bounds__(kBlock) void k_wide_select(WideArgs a) {
   const int2 ch = a.children[a.frontier[i].x];
   int r[4] = {ch.x, ch.y, kWideEmpty, kWideEmpty};
   int cnt = 2;
-  for (int step = 0; step < 2; ++step) {
+  if (a.dp_choice) {
+    // follow the cost-optimal cut: the node's four slots split k : 4 - k between its children, and a
+    // child with j > 1 slots is opened when that is cheaper
+    int js[4] = {int((a.dp_choice[a.frontier[i].x] >> 6) & 3u), 0, 0, 0};
+    js[1] = 4 - js[0];
+    for (int step = 0; step < 2; ++step) {
+      int p = -1;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (p < 0 && k < cnt && r[k] >= 0 && js[k] > 1 && ((a.dp_choice[r[k]] >> (3 * (js[k] - 2) + 2)) & 1u)) p = k;
+      if (p < 0) break;
+      const int2 c = a.children[r[p]];
+      const int kk = int((a.dp_choice[r[p]] >> (3 * (js[p] - 2))) & 3u);
+      const int jj = js[p];
+#pragma unroll
+      for (int k = 3; k > 0; --k)
+        if (k > p + 1 && k <= cnt) {
+          r[k] = r[k - 1];
+          js[k] = js[k - 1];
+        }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k == p) {
+          r[k] = c.x;
+          js[k] = kk;
+        }
+        if (k == p + 1) {
+          r[k] = c.y;
+          js[k] = jj - kk;
+        }
+      }
+      ++cnt;
+    }
+  } else
+    for (int step = 0; step < 2; ++step) {
     int best = -1;
     float best_area = -1.f;
 #pragma unroll
@@ -845,6 +938,8 @@ BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool
       p.ploc_nn_off = take(size_t(T) * 4);
       p.ploc_keep_off = take(size_t(T + 1) * 4);
       p.ploc_merge_off = take(size_t(T + 1) * 4);
+      p.dp_cost_off = take(size_t(T) * 16);
+      p.dp_choice_off = take(size_t(T) * 4);
     }
   }
   p.scratch_bytes = off;
@@ -957,6 +1052,8 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
       int32_t* parent = reinterpret_cast<int32_t*>(scratch + plan.parent_off);
       uint32_t* flags = reinterpret_cast<uint32_t*>(scratch + plan.flags_off);
       float4* nodebox = reinterpret_cast<float4*>(scratch + plan.nodebox_off);
+      float4* dp_cost = nullptr;
+      uint32_t* dp_choice = nullptr;
       if (plan.ploc) {
         float4* c_lo[2] = {reinterpret_cast<float4*>(scratch + plan.ploc_lo_off[0]),
                            reinterpret_cast<float4*>(scratch + plan.ploc_lo_off[1])};
@@ -969,6 +1066,7 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
         uint32_t* merge = reinterpret_cast<uint32_t*>(scratch + plan.ploc_merge_off);
         k_ploc_init<<<blocks_for(T), kBlock, 0, stream>>>(i0, lo, hi, T, c_lo[0], c_hi[0], c_ref[0]);
         SRT_LAUNCH_CHECK();
+        std::vector<std::pair<int64_t, int64_t>> round_nodes;  // nodes each round created, in merge order
         int64_t n = T, next = T - 1;
         int cur = 0;
         for (int round = 0; n > 1; ++round) {
@@ -1001,11 +1099,19 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
           ca.nodebox = nodebox;
           k_ploc_compact<<<blocks_for(n), kBlock, 0, stream>>>(ca);
           SRT_LAUNCH_CHECK();
+          round_nodes.emplace_back(next - merges, merges);
           next -= merges;
           n -= merges;
           cur ^= 1;
         }
         if (next != 0) return hipErrorUnknown;  // T - 1 merges make a binary tree rooted at node 0
+        dp_cost = reinterpret_cast<float4*>(scratch + plan.dp_cost_off);
+        dp_choice = reinterpret_cast<uint32_t*>(scratch + plan.dp_choice_off);
+        for (const auto& rn : round_nodes) {  // children were created in earlier rounds
+          k_wide_dp<<<blocks_for(rn.second), kBlock, 0, stream>>>(children, nodebox, lo, hi, i0, dp_cost, dp_choice,
+                                                                  rn.first, rn.second);
+          SRT_LAUNCH_CHECK();
+        }
         SRT_CHECK(hipMemcpyAsync(&bounds, partial, sizeof(bounds), hipMemcpyDeviceToHost, stream));
         SRT_CHECK(hipStreamSynchronize(stream));
       } else {
@@ -1034,6 +1140,7 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
       wa.nint = reinterpret_cast<uint32_t*>(scratch + plan.nint_off);
       wa.nodes = reinterpret_cast<float4*>(storage + plan.nodes_off);
       wa.pad = coord_max * 0x1p-18f + 1e-20f;  // conservative box growth (slab and triangle-test rounding)
+      wa.dp_choice = dp_choice;
       int2* fr[2] = {reinterpret_cast<int2*>(scratch + plan.frontier_off[0]),
                      reinterpret_cast<int2*>(scratch + plan.frontier_off[1])};
       k_set_int2<<<1, 1, 0, stream>>>(fr[0], make_int2(0, 0));

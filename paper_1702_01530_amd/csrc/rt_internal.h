@@ -129,6 +129,7 @@ struct BuildPlan {
   size_t keys0_off, keys1_off, ids0_off, ids1_off, lo_off, hi_off, partial_off, hist_off, children_off,
       parent_off, flags_off, nodebox_off, status_off, range_off, frontier_off[2], sel_off, nint_off;
   size_t ploc_lo_off[2], ploc_hi_off[2], ploc_ref_off[2], ploc_nn_off, ploc_keep_off, ploc_merge_off;
+  size_t dp_cost_off, dp_choice_off;
   size_t scan_tmp_off;
   size_t scratch_bytes;
   int64_t num_blocks_prep, num_sort_blocks;
