@@ -12,11 +12,12 @@
 //      emission (split at the highest differing bit; equal codes split by index) and
 //   6. a bottom-up box refit (an atomic arrival counter per node, the second
 //      child to arrive unions both boxes and climbs on);
-//   7. top-down collapse into a 4-wide tree, one level per launch, with the
+//   7. a bottom-up surface-area cost table that picks the cheapest way to cut the
+//      binary tree into a 4-wide one (filled during the refit, or one launch per
+//      clustering round);
+//   8. top-down collapse into that 4-wide tree, one level per launch, with the
 //      children's boxes quantised to 8 bits on each node's own grid (64-byte
-//      nodes), and 48-byte triangle records in leaf order.  The clustering tree is
-//      cut where a bottom-up surface-area cost table says (one launch per
-//      clustering round); the Karras tree by the largest-area rule.
+//      nodes), and 48-byte triangle records in leaf order.
 // Every step is deterministic, so a scene always builds the same tree.
 
 #include <hip/hip_runtime.h>
@@ -409,15 +410,81 @@ __global__ __launch_bounds__(kBlock) void k_karras(const uint64_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------------------------
-// 6. Bottom-up refit
+// 6./7. Bottom-up refit and cost table
 // ---------------------------------------------------------------------------------------------
+
+__device__ inline float half_area(float4 lo, float4 hi) {
+  const float dx = hi.x - lo.x, dy = hi.y - lo.y, dz = hi.z - lo.z;
+  return dx * dy + dy * dz + dz * dx;
+}
+
+#ifndef SRT_DP_TRI_COST
+#define SRT_DP_TRI_COST 0.5f
+#endif
+// Cost-optimal cut of the binary tree into the 4-wide tree (surface-area model, as in Ylitie et al.
+// 2017): C(n, j) is the least expected cost of binary subtree n when it may take j slots of its BVH4
+// parent.  C(n, 1) = A(n) + D_n(4) (n becomes a BVH4 node whose four slots its two children share),
+// D_n(j) = min over k of C(a, k) + C(b, j - k), and C(n, j) = min(C(n, 1), D_n(j)) for j > 1 (n kept
+// whole, or opened across j slots).  A leaf costs its area times the relative cost of a triangle test,
+// whatever its slot count.  Choice bits per node, for j = 2, 3, 4 at bit 3 (j - 2): the split k
+// (2 bits) and whether opening wins.
+__device__ inline void dp_child_costs(int r, const float4* dp_cost, const float4* leaf_lo, const float4* leaf_hi,
+                                      const uint32_t* sorted_ids, float (&c)[4]) {
+  if (r < 0) {
+    const uint32_t id = sorted_ids[~r];
+    const float a = SRT_DP_TRI_COST * half_area(leaf_lo[id], leaf_hi[id]);
+    c[0] = c[1] = c[2] = c[3] = a;
+  } else {
+    const float4 v = dp_cost[r];
+    c[0] = v.x, c[1] = v.y, c[2] = v.z, c[3] = v.w;
+  }
+}
+
+// Fills the cost table entry of binary node n, whose box and children's entries are final.
+__device__ inline void dp_node(int64_t n, const int2* children, const float4* nodebox, const float4* leaf_lo,
+                               const float4* leaf_hi, const uint32_t* sorted_ids, float4* dp_cost,
+                               uint32_t* dp_choice) {
+  const int2 ch = children[n];
+  float ca[4], cb[4];
+  dp_child_costs(ch.x, dp_cost, leaf_lo, leaf_hi, sorted_ids, ca);
+  dp_child_costs(ch.y, dp_cost, leaf_lo, leaf_hi, sorted_ids, cb);
+  float D[5];
+  int K[5];
+  for (int j = 2; j <= 4; ++j) {
+    D[j] = INFINITY;
+    K[j] = 1;
+    for (int k = 1; k < j; ++k) {
+      const float c = ca[k - 1] + cb[j - k - 1];
+      if (c < D[j]) {
+        D[j] = c;
+        K[j] = k;
+      }
+    }
+  }
+  const float c1 = half_area(nodebox[2 * n], nodebox[2 * n + 1]) + D[4];
+  dp_cost[n] = make_float4(c1, fminf(c1, D[2]), fminf(c1, D[3]), fminf(c1, D[4]));
+  uint32_t choice = 0;
+  for (int j = 2; j <= 4; ++j) choice |= (uint32_t(K[j]) | (D[j] < c1 ? 4u : 0u)) << (3 * (j - 2));
+  dp_choice[n] = choice;
+}
+
+// The clustering tree's nodes of one round (children were made in earlier rounds).
+__global__ __launch_bounds__(kBlock) void k_wide_dp(const int2* __restrict__ children, const float4* nodebox,
+                                                    const float4* leaf_lo, const float4* leaf_hi,
+                                                    const uint32_t* sorted_ids, float4* dp_cost,
+                                                    uint32_t* dp_choice, int64_t first, int64_t count) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= count) return;
+  dp_node(first + i, children, nodebox, leaf_lo, leaf_hi, sorted_ids, dp_cost, dp_choice);
+}
 
 __global__ __launch_bounds__(kBlock) void k_refit(const int2* __restrict__ children,
                                                   const int32_t* __restrict__ parent,
                                                   const float4* __restrict__ leaf_lo, const float4* __restrict__ leaf_hi,
                                                   const uint32_t* __restrict__ sorted_ids, float4* nodebox,
                                                   uint32_t* flags, int64_t n, int32_t* __restrict__ max_depth,
-                                                  uint32_t* __restrict__ status) {
+                                                  uint32_t* __restrict__ status, float4* dp_cost,
+                                                  uint32_t* dp_choice) {
   int64_t leaf = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (leaf >= n) return;
   int node = parent[n - 1 + leaf];
@@ -446,6 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_refit(const int2* __restrict__ child
     nodebox[2 * node] = make_float4(fminf(lo[0].x, lo[1].x), fminf(lo[0].y, lo[1].y), fminf(lo[0].z, lo[1].z), 0.f);
     nodebox[2 * node + 1] =
         make_float4(fmaxf(hi[0].x, hi[1].x), fmaxf(hi[0].y, hi[1].y), fmaxf(hi[0].z, hi[1].z), 0.f);
+    dp_node(node, children, nodebox, leaf_lo, leaf_hi, sorted_ids, dp_cost, dp_choice);
     if (node == 0) break;
     node = parent[node];
   }
@@ -580,12 +648,11 @@ __global__ __launch_bounds__(kBlock) void k_ploc_compact(PlocCompactArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// 7. Collapse into a 4-wide BVH, top-down one level at a time.  A BVH4 node takes a binary node's two
-// children and opens some of them into their own children (keeping left-to-right order) until it
-// holds up to four: where the cost table below says (clustering tree), or else by replacing the
-// largest-area internal child while fewer than four (Karras tree).  Internal children become the
-// next level's nodes; their indices come from a prefix sum, so the layout is deterministic and each
-// level's nodes are contiguous.
+// 8. Collapse into a 4-wide BVH, top-down one level at a time.  A BVH4 node takes a binary node's two
+// children and opens some of them into their own children (keeping left-to-right order) where the
+// cost table says, so it holds up to four.  Internal children become the next level's nodes; their
+// indices come from a prefix sum, so the layout is deterministic and each level's nodes are
+// contiguous.
 // ---------------------------------------------------------------------------------------------
 
 constexpr int kWideEmpty = INT32_MIN;
@@ -604,66 +671,9 @@ struct WideArgs {
   float4* nodes;         // 8 float4 per BVH4 node
   int64_t level_base;    // BVH4 index of the next level's first node
   float pad;
-  const uint32_t* dp_choice;  // per binary node: the cost-optimal cut (nullptr: largest-area rule)
+  const uint32_t* dp_choice;  // per binary node: the cost-optimal cut
 };
 
-__device__ inline float half_area(float4 lo, float4 hi) {
-  const float dx = hi.x - lo.x, dy = hi.y - lo.y, dz = hi.z - lo.z;
-  return dx * dy + dy * dz + dz * dx;
-}
-
-#ifndef SRT_DP_TRI_COST
-#define SRT_DP_TRI_COST 0.5f
-#endif
-// Cost-optimal collapse (surface-area model): C(n, j) is the least expected cost of binary subtree
-// n when it may take j slots of its BVH4 parent.  C(n, 1) = A(n) + D_n(4) (n becomes a BVH4 node
-// whose four slots are shared by its two children), D_n(j) = min over k of C(a, k) + C(b, j - k),
-// and C(n, j) = min(C(n, 1), D_n(j)) for j > 1 (n kept whole, or opened across j slots).  A leaf
-// costs its area times the relative cost of a triangle test in every slot count.  Nodes of one
-// clustering round are computed together, rounds in the order they merged (children first).
-// Choice bits per node, for j = 2, 3, 4 at bit 3 (j - 2): the split k (2 bits) and whether opening wins.
-__device__ inline void dp_child_costs(int r, const float4* dp_cost, const float4* leaf_lo, const float4* leaf_hi,
-                                      const uint32_t* sorted_ids, float c_tri, float (&c)[4]) {
-  if (r < 0) {
-    const uint32_t id = sorted_ids[~r];
-    const float a = c_tri * half_area(leaf_lo[id], leaf_hi[id]);
-    c[0] = c[1] = c[2] = c[3] = a;
-  } else {
-    const float4 v = dp_cost[r];
-    c[0] = v.x, c[1] = v.y, c[2] = v.z, c[3] = v.w;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_wide_dp(const int2* __restrict__ children, const float4* nodebox,
-                                                    const float4* leaf_lo, const float4* leaf_hi,
-                                                    const uint32_t* sorted_ids, float4* dp_cost,
-                                                    uint32_t* dp_choice, int64_t first, int64_t count) {
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= count) return;
-  const int64_t n = first + i;
-  const int2 ch = children[n];
-  float ca[4], cb[4];
-  dp_child_costs(ch.x, dp_cost, leaf_lo, leaf_hi, sorted_ids, SRT_DP_TRI_COST, ca);
-  dp_child_costs(ch.y, dp_cost, leaf_lo, leaf_hi, sorted_ids, SRT_DP_TRI_COST, cb);
-  float D[5];
-  int K[5];
-  for (int j = 2; j <= 4; ++j) {
-    D[j] = INFINITY;
-    K[j] = 1;
-    for (int k = 1; k < j; ++k) {
-      const float c = ca[k - 1] + cb[j - k - 1];
-      if (c < D[j]) {
-        D[j] = c;
-        K[j] = k;
-      }
-    }
-  }
-  const float c1 = half_area(nodebox[2 * n], nodebox[2 * n + 1]) + D[4];
-  dp_cost[n] = make_float4(c1, fminf(c1, D[2]), fminf(c1, D[3]), fminf(c1, D[4]));
-  uint32_t choice = 0;
-  for (int j = 2; j <= 4; ++j) choice |= (uint32_t(K[j]) | (D[j] < c1 ? 4u : 0u)) << (3 * (j - 2));
-  dp_choice[n] = choice;
-}
 
 __global__ __launch_bounds__(kBlock) void k_wide_select(WideArgs a) {
   int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -671,63 +681,35 @@ __global__ __launch_bounds__(kBlock) void k_wide_select(WideArgs a) {
   const int2 ch = a.children[a.frontier[i].x];
   int r[4] = {ch.x, ch.y, kWideEmpty, kWideEmpty};
   int cnt = 2;
-  if (a.dp_choice) {
-    // follow the cost-optimal cut: the node's four slots split k : 4 - k between its children, and a
-    // child with j > 1 slots is opened when that is cheaper
-    int js[4] = {int((a.dp_choice[a.frontier[i].x] >> 6) & 3u), 0, 0, 0};
-    js[1] = 4 - js[0];
-    for (int step = 0; step < 2; ++step) {
-      int p = -1;
+  // follow the cost-optimal cut: the node's four slots split k : 4 - k between its children, and a
+  // child with j > 1 slots is opened when that is cheaper
+  int js[4] = {int((a.dp_choice[a.frontier[i].x] >> 6) & 3u), 0, 0, 0};
+  js[1] = 4 - js[0];
+  for (int step = 0; step < 2; ++step) {
+    int p = -1;
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (p < 0 && k < cnt && r[k] >= 0 && js[k] > 1 && ((a.dp_choice[r[k]] >> (3 * (js[k] - 2) + 2)) & 1u)) p = k;
-      if (p < 0) break;
-      const int2 c = a.children[r[p]];
-      const int kk = int((a.dp_choice[r[p]] >> (3 * (js[p] - 2))) & 3u);
-      const int jj = js[p];
-#pragma unroll
-      for (int k = 3; k > 0; --k)
-        if (k > p + 1 && k <= cnt) {
-          r[k] = r[k - 1];
-          js[k] = js[k - 1];
-        }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (k == p) {
-          r[k] = c.x;
-          js[k] = kk;
-        }
-        if (k == p + 1) {
-          r[k] = c.y;
-          js[k] = jj - kk;
-        }
-      }
-      ++cnt;
-    }
-  } else
-    for (int step = 0; step < 2; ++step) {
-    int best = -1;
-    float best_area = -1.f;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (k < cnt && r[k] >= 0) {
-        const float ar = half_area(a.nodebox[2 * r[k]], a.nodebox[2 * r[k] + 1]);
-        if (ar > best_area) {
-          best_area = ar;
-          best = k;
-        }
-      }
-    }
-    if (best < 0) break;
-    const int2 c = a.children[r[best]];
-    // insert c.y after position best, shifting the tail right
+    for (int k = 0; k < 4; ++k)
+      if (p < 0 && k < cnt && r[k] >= 0 && js[k] > 1 && ((a.dp_choice[r[k]] >> (3 * (js[k] - 2) + 2)) & 1u)) p = k;
+    if (p < 0) break;
+    const int2 c = a.children[r[p]];
+    const int kk = int((a.dp_choice[r[p]] >> (3 * (js[p] - 2))) & 3u);
+    const int jj = js[p];
 #pragma unroll
     for (int k = 3; k > 0; --k)
-      if (k > best + 1 && k <= cnt) r[k] = r[k - 1];
+      if (k > p + 1 && k <= cnt) {
+        r[k] = r[k - 1];
+        js[k] = js[k - 1];
+      }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (k == best) r[k] = c.x;
-      if (k == best + 1) r[k] = c.y;
+      if (k == p) {
+        r[k] = c.x;
+        js[k] = kk;
+      }
+      if (k == p + 1) {
+        r[k] = c.y;
+        js[k] = jj - kk;
+      }
     }
     ++cnt;
   }
@@ -924,6 +906,8 @@ BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool
       p.parent_off = take(size_t(2 * T) * 4);
       p.flags_off = take(size_t(T) * 4);
     }
+    p.dp_cost_off = take(size_t(T) * 16);
+    p.dp_choice_off = take(size_t(T) * 4);
     p.frontier_off[0] = take(size_t(T) * 8);
     p.frontier_off[1] = take(size_t(T) * 8);
     p.sel_off = take(size_t(T) * 16);
@@ -938,8 +922,6 @@ BuildPlan plan_build(int64_t T, int64_t S, int64_t P, int64_t M, int64_t L, bool
       p.ploc_nn_off = take(size_t(T) * 4);
       p.ploc_keep_off = take(size_t(T + 1) * 4);
       p.ploc_merge_off = take(size_t(T + 1) * 4);
-      p.dp_cost_off = take(size_t(T) * 16);
-      p.dp_choice_off = take(size_t(T) * 4);
     }
   }
   p.scratch_bytes = off;
@@ -1052,8 +1034,8 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
       int32_t* parent = reinterpret_cast<int32_t*>(scratch + plan.parent_off);
       uint32_t* flags = reinterpret_cast<uint32_t*>(scratch + plan.flags_off);
       float4* nodebox = reinterpret_cast<float4*>(scratch + plan.nodebox_off);
-      float4* dp_cost = nullptr;
-      uint32_t* dp_choice = nullptr;
+      float4* dp_cost = reinterpret_cast<float4*>(scratch + plan.dp_cost_off);
+      uint32_t* dp_choice = reinterpret_cast<uint32_t*>(scratch + plan.dp_choice_off);
       if (plan.ploc) {
         float4* c_lo[2] = {reinterpret_cast<float4*>(scratch + plan.ploc_lo_off[0]),
                            reinterpret_cast<float4*>(scratch + plan.ploc_lo_off[1])};
@@ -1105,8 +1087,6 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
           cur ^= 1;
         }
         if (next != 0) return hipErrorUnknown;  // T - 1 merges make a binary tree rooted at node 0
-        dp_cost = reinterpret_cast<float4*>(scratch + plan.dp_cost_off);
-        dp_choice = reinterpret_cast<uint32_t*>(scratch + plan.dp_choice_off);
         for (const auto& rn : round_nodes) {  // children were created in earlier rounds
           k_wide_dp<<<blocks_for(rn.second), kBlock, 0, stream>>>(children, nodebox, lo, hi, i0, dp_cost, dp_choice,
                                                                   rn.first, rn.second);
@@ -1120,7 +1100,8 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
         SRT_LAUNCH_CHECK();
         k_fill<uint32_t><<<blocks_for(T - 1), kBlock, 0, stream>>>(flags, 0u, T - 1);
         SRT_LAUNCH_CHECK();
-        k_refit<<<blocks_for(T), kBlock, 0, stream>>>(children, parent, lo, hi, i0, nodebox, flags, T, dmax, status);
+        k_refit<<<blocks_for(T), kBlock, 0, stream>>>(children, parent, lo, hi, i0, nodebox, flags, T, dmax, status,
+                                                      dp_cost, dp_choice);
         SRT_LAUNCH_CHECK();
         // read back the scene bounds for the padding
         SRT_CHECK(hipMemcpyAsync(&bounds, partial, sizeof(bounds), hipMemcpyDeviceToHost, stream));
