@@ -175,10 +175,8 @@ enum {
   RT_COUNT_CLOSEST_TRIS = 4,  /* triangle tests by closest-hit rays (RT_FLAG_COUNT_WORK) */
   RT_COUNT_ANY_NODES = 5,     /* BVH node visits by shadow rays (RT_FLAG_COUNT_WORK) */
   RT_COUNT_ANY_TRIS = 6,      /* triangle tests by shadow rays (RT_FLAG_COUNT_WORK) */
-  RT_COUNT_ERRORS = 7,        /* internal consistency checks that fired, as flag bits added per render:
-                                 1 a ray stopped on a corrupt tree reference or a full stack, 2 a traversal
-                                 kernel found its argument layout changed (always 0 unless the library is
-                                 broken) */
+  RT_COUNT_ERRORS = 7,        /* launches that stopped a ray on an internal consistency check (always 0
+                                 unless the library is broken) */
   RT_NUM_COUNTERS = 8
 };
 

@@ -506,12 +506,6 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
   __shared__ float4 lnodes[kLdsNodes > 0 ? 4 * kLdsNodes : 1];
   const int lane = lane_id();
   const int gtid = blockIdx.x * kBlock + threadIdx.x;
-  // kernel_args reads the argument segment directly: should its layout ever differ from the
-  // parameter's, flag it and stop before any ray is touched (the same decision in every thread)
-  if (kernel_args().ctr != a.ctr || kernel_args().trace_threads != a.trace_threads) {
-    if (threadIdx.x == 0) atomicOr(&a.ctr->error, 2u);
-    return;
-  }
   Stack st{&lstack[threadIdx.x], a.gstack + gtid, a.trace_threads, 0, false};
   const int LS = a.lstride;
   int kc = 0;  // nodes held in lnodes (the same for the whole block)
