@@ -462,7 +462,7 @@ def test_terrain212k_1080p_sampled(torch_cuda, terrain_212k, accel):
 def test_terrain3m_1080p_sampled(torch_cuda, terrain_3m):
     """The benchmark workload at its full size, in the launch configuration the benchmark times."""
     scene, cam = terrain_3m
-    samples = sg.sample_paths(cam, 384, seed=31)
+    samples = sg.sample_paths(cam, 1024, seed=31)
     check_parity(torch_cuda, scene, cam, samples=samples)
 
 
@@ -470,7 +470,7 @@ def test_terrain3m_4k_sampled(torch_cuda, terrain_3m):
     """The 3.4M-triangle scene at 3840x2160 per eye (the roofline configuration), sampled paths."""
     scene, cam = terrain_3m
     cam = cam.resized(3840, 2160)
-    samples = sg.sample_paths(cam, 256, seed=41)
+    samples = sg.sample_paths(cam, 512, seed=41)
     check_parity(torch_cuda, scene, cam, samples=samples)
 
 
