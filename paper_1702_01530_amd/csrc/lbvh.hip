@@ -593,6 +593,13 @@ __global__ __launch_bounds__(kBlock) void k_ploc_nn(const float4* __restrict__ c
       bj = int32_t(j);
     }
   }
+  // A merge that does not grow the box (coincident or nested boxes) prefers the parity partner i^1
+  // when it ties: runs of coincident triangles then pair up as (0,1), (2,3), ... and halve every
+  // round, instead of all choosing one cluster and merging one pair per round into a chain.
+  const int64_t partner = i ^ 1;
+  if (partner < n && best <= merged_area(alo, ahi, alo, ahi) &&
+      merged_area(alo, ahi, s_lo[si + int(partner - i)], s_hi[si + int(partner - i)]) == best)
+    bj = int32_t(partner);
   nn[i] = bj;
 }
 

@@ -274,6 +274,34 @@ def test_degenerate_scenes(torch_cuda):
             check_parity(torch, scene, c, allow_min_one=False)
 
 
+@pytest.mark.parametrize("accel", ["lbvh", "lbvh_karras"])
+def test_coincident_and_zero_area_triangles(torch_cuda, accel):
+    """Hundreds of copies of one triangle (equal Morton codes, equal boxes, exact ties in t that only the
+    smaller id decides), zero-area triangles (collinear and point-like: never hit) and a mirror floor."""
+    rng = np.random.default_rng(7)
+    front = [[-1.0, 0.0, 4.0], [1.0, 0.0, 4.0], [0.0, 2.0, 4.0]]
+    tris = [front] * 300
+    for _ in range(60):
+        # zero area exactly in any precision: three points on a line parallel to an axis, integer
+        # coordinates (the edge vectors are (1,0,0) and (2,0,0), so the determinant is exactly 0), and
+        # a point repeated three times
+        a = rng.integers(-3, 4, 3).astype(np.float64) + [0, 1, 5]
+        axis = np.eye(3)[rng.integers(0, 3)]
+        tris.append([list(a), list(a + axis), list(a + 2 * axis)])
+        tris.append([list(a)] * 3)
+    tris.append([[-8, -0.5, 0], [8, -0.5, 0], [0, -0.5, 16]])
+    mats = [0] * 300 + [0] * 120 + [1]
+    scene = make_scene(tris=tris, tri_mat=mats, lights=[[0, 6, 1, 1, 1, 1], [3, 4, 2, 0.5, 0.5, 0.5]],
+                       materials=[material(), material(kd=(0.2, 0.2, 0.2), kr=(0.6, 0.6, 0.6))],
+                       ambient=(0.05,) * 3, name="coincident")
+    cam = mono_camera(center=(0, 1, 0), width=48, height=32, depth=3, baseline=0.065, convergence=4.0)
+    g, orc, res = check_parity(torch_cuda, scene, cam, accel=accel, allow_min_one=False)
+    ids = g["path_prims"].reshape(-1)
+    assert (ids == 0).any() and (ids == 420).any()  # the front triangle and the floor are both seen
+    assert not np.isin(ids, np.arange(1, 300)).any()  # a copy of the front triangle never beats copy 0
+    assert not np.isin(ids, np.arange(300, 420)).any()  # zero-area triangles are never hit
+
+
 def test_headlight_lambert_closed_form_gpu(torch_cuda):
     """Sphere lit from the eye: radiance = rho I cos(theta) + ks I max(0, cos 2theta)^n (closed form)."""
     c = np.array([0.3, 0.9, 6.0])
