@@ -302,6 +302,28 @@ def test_coincident_and_zero_area_triangles(torch_cuda, accel):
     assert not np.isin(ids, np.arange(300, 420)).any()  # zero-area triangles are never hit
 
 
+@pytest.mark.parametrize("accel", ["lbvh", "lbvh_karras"])
+def test_flat_scene(torch_cuda, accel):
+    """Every triangle in the plane y = 0 (boxes of zero height: the quantisation grid and the padding
+    must still give every box a slab the rays can enter), a mirror stripe, grazing and axis-parallel
+    rays."""
+    n = 24
+    tris, mats = [], []
+    for i in range(n):
+        for j in range(n):
+            x0, z0 = -6.0 + 0.5 * i, 0.5 * j
+            q = [[x0, 0.0, z0], [x0 + 0.5, 0.0, z0], [x0 + 0.5, 0.0, z0 + 0.5], [x0, 0.0, z0 + 0.5]]
+            tris += [[q[0], q[1], q[2]], [q[0], q[2], q[3]]]
+            mats += [1 if i % 6 == 0 else 0] * 2
+    scene = make_scene(tris=tris, tri_mat=mats, lights=[[0, 3, 4, 1, 1, 1], [-4, 0.5, 8, 0.6, 0.6, 0.6]],
+                       materials=[material(kd=(0.7, 0.6, 0.5), ks=(0.3, 0.3, 0.3), n=16),
+                                  material(kd=(0.1, 0.1, 0.1), kr=(0.8, 0.8, 0.8))],
+                       ambient=(0.05,) * 3, name="flat")
+    # eye height 0.25 over the plane: most rays graze it; the centre column of an odd width is axis-parallel
+    cam = mono_camera(center=(0, 0.25, -1), width=41, height=21, depth=2, baseline=0.065, convergence=3.0)
+    check_parity(torch_cuda, scene, cam, accel=accel)
+
+
 def test_headlight_lambert_closed_form_gpu(torch_cuda):
     """Sphere lit from the eye: radiance = rho I cos(theta) + ks I max(0, cos 2theta)^n (closed form)."""
     c = np.array([0.3, 0.9, 6.0])
