@@ -302,6 +302,26 @@ def test_coincident_and_zero_area_triangles(torch_cuda, accel):
     assert not np.isin(ids, np.arange(300, 420)).any()  # zero-area triangles are never hit
 
 
+def test_maximum_lights_and_depth(torch_cuda):
+    """RT_MAX_LIGHTS point lights (eight shadow queues per depth) and RT_MAX_DEPTH mirror bounces: mirror
+    planes on both sides and at the back keep most paths bouncing to the last depth."""
+    import dataclasses
+    from paper_1702_01530_amd import rt
+    scene, cam = sg.make_small_terrain(seed=13, grid=20, n_spheres=5, level=1, lights=1, depth=3)
+    L = 8
+    assert rt.RT_MAX_LIGHTS == L and rt.RT_MAX_DEPTH == 8
+    ang = np.linspace(0.0, 2.0 * np.pi, L, endpoint=False)
+    lights = [[8 * np.cos(a), 5 + 2 * (k % 3), 8 + 8 * np.sin(a), 0.25, 0.2 + 0.02 * k, 0.15] for k, a in enumerate(ang)]
+    scene = scene.with_lights(lights)
+    M = scene.materials.shape[0]
+    mirror = np.float32([[0.05, 0.05, 0.05, 0, 0, 0, 0.8, 0.8, 0.8, 16]])
+    scene = dataclasses.replace(scene, planes=np.float32([[1, 0, 0, -9], [-1, 0, 0, -9], [0, 0, -1, -30]]),
+                                plane_material=np.uint32([M, M, M]), materials=np.vstack([scene.materials, mirror]))
+    cam = cam.resized(48, 32).with_(max_depth=8)
+    g, orc, _ = check_parity(torch_cuda, scene, cam)
+    assert (orc["path_prims"][:, 8] >= 0).sum() > 1000  # most paths bounce to the last depth
+
+
 @pytest.mark.parametrize("accel", ["lbvh", "lbvh_karras"])
 def test_flat_scene(torch_cuda, accel):
     """Every triangle in the plane y = 0 (boxes of zero height: the quantisation grid and the padding
