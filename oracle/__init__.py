@@ -69,18 +69,20 @@ def lib():
         _lib = C.CDLL(build())
         _lib.orc_render.restype = C.c_int
         _lib.orc_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_void_p, C.c_int64, C.c_int32,
-                                    C.c_int32, C.POINTER(_Output)]
+                                    C.POINTER(_Output)]
         _lib.orc_primary_ray.argtypes = [C.POINTER(_Camera), C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
         _lib.orc_primary_ray.restype = None
         d = C.c_void_p
-        _lib.orc_intersect_triangle.argtypes = [d, d, d, d, d, C.c_double, C.c_double, d, d, d]
+        _lib.orc_intersect_triangle.argtypes = [d, d, d, d, d, C.c_double, C.c_double, d, d, d, d]
         _lib.orc_intersect_triangle.restype = C.c_int32
-        _lib.orc_intersect_sphere.argtypes = [d, d, d, C.c_double, C.c_double, C.c_double, d]
+        _lib.orc_intersect_sphere.argtypes = [d, d, d, C.c_double, C.c_double, C.c_double, d, d]
         _lib.orc_intersect_sphere.restype = C.c_int32
-        _lib.orc_intersect_plane.argtypes = [d, d, d, C.c_double, C.c_double, C.c_double, d]
+        _lib.orc_intersect_plane.argtypes = [d, d, d, C.c_double, C.c_double, C.c_double, d, d]
         _lib.orc_intersect_plane.restype = C.c_int32
         _lib.orc_closest_hits.argtypes = [C.POINTER(_Scene), d, d, C.c_int64, C.c_double, d, d, d, d]
         _lib.orc_closest_hits.restype = C.c_int32
+        _lib.orc_occluded.argtypes = [C.POINTER(_Scene), d, d, C.c_int64, C.c_double, d, d, d, d]
+        _lib.orc_occluded.restype = C.c_int32
     return _lib
 
 
@@ -141,7 +143,7 @@ def default_threads() -> int:
     return max(1, min(16, os.cpu_count() or 1))
 
 
-def render(scene, cam, samples=None, nthreads=None, fp32_rays=False) -> dict:
+def render(scene, cam, samples=None, nthreads=None) -> dict:
     """Oracle render of the sampled paths (None: every path of both eyes)."""
     held = _Held()
     s = _scene_struct(scene, held)
@@ -166,8 +168,7 @@ def render(scene, cam, samples=None, nthreads=None, fp32_rays=False) -> dict:
     for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state", "hit_margin", "shadow_margin",
               "shadow_contrib"):
         setattr(o, k, _ptr(res[k]))
-    rc = lib().orc_render(C.byref(s), C.byref(c), _ptr(samp), n, int(nthreads or default_threads()),
-                          1 if fp32_rays else 0, C.byref(o))
+    rc = lib().orc_render(C.byref(s), C.byref(c), _ptr(samp), n, int(nthreads or default_threads()), C.byref(o))
     if rc != 0:
         raise ValueError("oracle render rejected its arguments")
     res["ray_counts"] = np.array(list(o.ray_counts), np.int64)
@@ -187,27 +188,35 @@ def _v(x):
     return np.ascontiguousarray(x, dtype=np.float64)
 
 
-def intersect_triangle(O, d, v0, v1, v2, tmin=0.0, tmax=np.inf):
+def intersect_triangle(O, d, v0, v1, v2, tmin=0.0, tmax=np.inf, with_margin=False):
+    """(hit, t, u, v) of one ray and one triangle; with_margin adds the decision margin."""
     O, d, v0, v1, v2 = map(_v, (O, d, v0, v1, v2))
-    t, u, v = np.zeros(1), np.zeros(1), np.zeros(1)
+    t, u, v, m = np.zeros(1), np.zeros(1), np.zeros(1), np.zeros(1)
     hit = lib().orc_intersect_triangle(O.ctypes.data, d.ctypes.data, v0.ctypes.data, v1.ctypes.data,
-                                       v2.ctypes.data, tmin, tmax, t.ctypes.data, u.ctypes.data, v.ctypes.data)
-    return bool(hit), float(t[0]), float(u[0]), float(v[0])
+                                       v2.ctypes.data, tmin, tmax, t.ctypes.data, u.ctypes.data, v.ctypes.data,
+                                       m.ctypes.data)
+    res = (bool(hit), float(t[0]), float(u[0]), float(v[0]))
+    return res + (float(m[0]),) if with_margin else res
 
 
-def intersect_sphere(O, d, c, r, tmin=0.0, tmax=np.inf):
+def intersect_sphere(O, d, c, r, tmin=0.0, tmax=np.inf, with_margin=False):
+    """(hit, t) of one ray (unit d) and one sphere; with_margin adds disc / r^2."""
     O, d, c = map(_v, (O, d, c))
-    t = np.zeros(1)
-    hit = lib().orc_intersect_sphere(O.ctypes.data, d.ctypes.data, c.ctypes.data, float(r), tmin, tmax, t.ctypes.data)
-    return bool(hit), float(t[0])
+    t, m = np.zeros(1), np.zeros(1)
+    hit = lib().orc_intersect_sphere(O.ctypes.data, d.ctypes.data, c.ctypes.data, float(r), tmin, tmax, t.ctypes.data,
+                                     m.ctypes.data)
+    res = (bool(hit), float(t[0]))
+    return res + (float(m[0]),) if with_margin else res
 
 
-def intersect_plane(O, d, n, dist, tmin=0.0, tmax=np.inf):
+def intersect_plane(O, d, n, dist, tmin=0.0, tmax=np.inf, with_margin=False):
+    """(hit, t) of one ray and the plane n.x = dist; with_margin adds the sine of the grazing angle."""
     O, d, n = map(_v, (O, d, n))
-    t = np.zeros(1)
+    t, m = np.zeros(1), np.zeros(1)
     hit = lib().orc_intersect_plane(O.ctypes.data, d.ctypes.data, n.ctypes.data, float(dist), tmin, tmax,
-                                    t.ctypes.data)
-    return bool(hit), float(t[0])
+                                    t.ctypes.data, m.ctypes.data)
+    res = (bool(hit), float(t[0]))
+    return res + (float(m[0]),) if with_margin else res
 
 
 def encode8(x, exposure=1.0):
@@ -254,3 +263,20 @@ def closest_hits(scene, O, d, tmin=0.0, exclude=None):
     lib().orc_closest_hits(C.byref(s), O.ctypes.data, d.ctypes.data, n, float(tmin), _ptr(ex), t.ctypes.data,
                            p.ctypes.data, m.ctypes.data)
     return t, p, m
+
+
+def occluded(scene, O, d, tmax, tmin=1e-4, exclude=None):
+    """Occlusion (t in (tmin, tmax)) of explicit segments [n,3] by any primitive but `exclude`, and the
+    decision margin of each."""
+    held = _Held()
+    s = _scene_struct(scene, held)
+    O = _v(O).reshape(-1, 3)
+    d = _v(d).reshape(-1, 3)
+    n = O.shape[0]
+    tm = np.ascontiguousarray(np.broadcast_to(np.asarray(tmax, np.float64), (n,)))
+    ex = None if exclude is None else np.ascontiguousarray(exclude, dtype=np.int64)
+    occ = np.zeros(n, np.int32)
+    m = np.zeros(n)
+    lib().orc_occluded(C.byref(s), O.ctypes.data, d.ctypes.data, n, float(tmin), tm.ctypes.data, _ptr(ex),
+                       occ.ctypes.data, m.ctypes.data)
+    return occ.astype(bool), m
