@@ -24,29 +24,45 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s and stereo frames/s (1080p, 2M tris) at 1 GPU; p50/p99 latency served"
 HBM_PEAK_GBS = 8000.0
+# VALU: 256 CUs x 4 SIMDs x 16 lanes, one lane operation per lane per clock at 2.4 GHz (an FMA counts once;
+# packed FP32 is not used by this build).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
-# Algorithmic bytes (what the traversal must read and write if nothing were cached).
-# A node visit reads the node's child boxes and child references: 56 B of a 64 B four-wide node with
-# quantised boxes (corner + exponents 16 B, references 16 B, 24 B of 8-bit grid coordinates), 112 B
-# of a 128 B four-wide node with FP32 boxes (six 16 B box planes + 16 B of references).
-NODE_VISIT_BYTES = {64: 56, 128: 112}  # node record size -> bytes one visit reads
+# Algorithmic work of the traversal: what the method has to compute per unit, however it is coded.
+# A visit of a four-wide node is four ray-box slab tests; each is 6 plane distances (one FMA each, the ray
+# origin pre-scaled by 1/d), 3 max and 3 min for the entry and exit distances (against tmin and tmax) and
+# one compare: 13 lane operations per child box, 52 per visit.  A Moller-Trumbore triangle test is 38:
+# T = o - v0 (3), P = d x e2 (6), det (3), 1/det (1), u (4), Q = T x e1 (6), v (4), t (4), the four
+# barycentric checks with u + v (5) and the t range (2).
+OPS_PER_NODE_VISIT = 52
+OPS_PER_TRI_TEST = 38
+# Algorithmic bytes (what the traversal reads and writes if nothing were cached): a visit reads the whole
+# node record (64 B four-wide quantised, 128 B four-wide FP32), a triangle test its 48 B record.
+NODE_VISIT_BYTES = {64: 64, 128: 128}  # node record size -> bytes one visit reads
 TRI_BYTES = 48       # one triangle record test
 CLOSEST_RAY_IO = 32 + 8   # ray in (origin+path, direction+exclude) + hit out (t, key)
 ANY_RAY_IO = 32 + 1       # shadow record in + visibility byte out
+COUNTER_SOURCES = ["paper_1702_01530_amd/csrc/render.hip", "paper_1702_01530_amd/csrc/lbvh.hip",
+                   "paper_1702_01530_amd/csrc/rt_internal.h", "paper_1702_01530_amd/csrc/ploc_rule.h"]
 
 
-def measured_traffic(workload_name: str):
-    """HBM bytes per k_trace launch from the committed rocprofv3 counter runs, if the kernel sources
-    are still the ones that were profiled (else None)."""
+def sources_sha256(sources) -> str:
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_trace_{workload_name}_traffic.json")
+    h = hashlib.sha256()
+    for src in sources:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return h.hexdigest()
+
+
+def stored_counters(workload_name: str):
+    """The traversal kernel's rocprofv3 counter figures committed under profiles/ (HBM bytes per launch,
+    VALU instructions, lane utilisation), if the kernel sources are still the ones that were profiled
+    (else None): counters are never carried over to a changed kernel."""
+    path = os.path.join(ROOT, "profiles", f"k_trace_{workload_name}_counters.json")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
-    h = hashlib.sha256()
-    for src in t["sources"]:
-        h.update(open(os.path.join(ROOT, src), "rb").read())
-    return t["hbm_bytes_per_launch"] if h.hexdigest() == t["sources_sha256"] else None
+    return t if sources_sha256(t["sources"]) == t["sources_sha256"] else None
 
 
 def log(*a):
@@ -67,25 +83,53 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(scene, cam, target_s: float = 15.0) -> dict:
-    """The FP64 brute-force oracle on a seeded sample of the same frame's paths, timed on the host."""
-    import numpy as np
+def cpu_threads() -> int:
+    """Threads for the host oracle: the CPUs this process may run on, at most 16 (a GPU's share of the host)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
+
+
+def cpu_baseline(scene, cam, rays_per_frame: int, target_s: float = 15.0):
+    """The FP64 brute-force oracle as it stands, timed on the host on a seeded sample of the same frame's paths:
+    with every thread of the process's CPU share (at most 16) and with one thread.  Returns the baseline
+    record, and the oracle's result on the sample (for the parity check of the GPU frame)."""
     import oracle
     import scenegen as sg
-    threads = oracle.default_threads()
+    threads = cpu_threads()
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = None
     n = threads * 2
     while True:
+        samples = sg.sample_paths(cam, n, seed=99)
         t0 = time.perf_counter()
-        r = oracle.render(scene, cam, samples=sg.sample_paths(cam, n, seed=99), nthreads=threads)
+        r = oracle.render(scene, cam, samples=samples, nthreads=threads)
         dt = time.perf_counter() - t0
         if dt >= target_s * 0.66 or n >= 2 * cam.width * cam.height:
             break
         n = int(min(2 * cam.width * cam.height, max(2 * n, n * target_s / max(dt, 1e-3))))
     rays = int(r["ray_counts"].sum())
-    return {"value": rays / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+    rate = rays / dt
+    # one thread, on a smaller seeded sample of the same frame (a fifth of the time budget)
+    n1 = max(4, int(n * (target_s / 5) / (dt * threads)))
+    t0 = time.perf_counter()
+    r1 = oracle.render(scene, cam, samples=sg.sample_paths(cam, n1, seed=98), nthreads=1)
+    dt1 = time.perf_counter() - t0
+    rays1 = int(r1["ray_counts"].sum())
+    base = {"value": rate / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} seeded paths of the same stereo frame ({rays} rays, FP64 brute force over all "
-                      f"{scene.num_prims} primitives per ray, {dt:.1f} s)",
-            "seconds": dt, "paths": n}
+                      f"{scene.num_prims} primitives per ray, {dt:.1f} s on {threads} threads)",
+            "seconds": dt, "paths": n, "rays": rays,
+            "ray_primitive_tests_per_s": rays * scene.num_prims / dt,
+            "host_nproc": os.cpu_count(), "host_cpus_available": avail,
+            "one_thread": {"value": rays1 / dt1 / 1e6, "unit": "Mrays/s", "paths": n1, "rays": rays1,
+                           "seconds": dt1},
+            "frame_seconds": rays_per_frame / rate, "frame_seconds_is": "extrapolated from the sample's rate"}
+    return base, r
 
 
 def bench_batch(args):
@@ -371,6 +415,76 @@ def bench_builders(args):
     print(json.dumps(res), flush=True)
 
 
+def copy_peak_gbs(dev) -> float:
+    """Device-to-device copy bandwidth (bytes read + written per second) of a 1 GiB buffer: the HBM rate a
+    plain streaming kernel reaches here, beside the 8 TB/s datasheet peak."""
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device=dev)
+    b = torch.empty(n, dtype=torch.uint8, device=dev)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del a, b
+    return 2 * n / (ms * 1e-3) / 1e9
+
+
+def summarize_counters(args):
+    """Reads the rocprofv3 counter CSVs of the traversal kernel's runs and writes its per-launch figures:
+    HBM bytes (FETCH_SIZE and WRITE_SIZE, scaled by what the same counters read for a 1 GiB copy), VALU
+    wave instructions and lane utilisation.  The JSON carries a hash of the kernel sources."""
+    import csv
+    import glob
+    import re
+    if len(args.pmc_dirs) != 5:
+        raise SystemExit("--pmc-dirs needs the fetch, write, copy-fetch, copy-write and SQ run directories")
+    kre = re.compile(r"k_trace<false, false>")
+    cre = re.compile(r"copyBuffer|copy_kernel|elementwise")
+
+    def load(d, kernel_re):
+        per = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                name = r.get("Kernel_Name", "")
+                if not kernel_re.search(name):
+                    continue
+                key = (f, r.get("Dispatch_Id"))
+                row = per.setdefault(key, {})
+                row[r["Counter_Name"]] = row.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        if not per:
+            raise SystemExit(f"no matching dispatches under {d}")
+        return list(per.values())
+
+    def mean(rows, c):
+        return sum(r[c] for r in rows) / len(rows)
+
+    fetch, write, cfetch, cwrite, sq = (load(d, kre if i in (0, 1, 4) else cre)
+                                        for i, d in enumerate(args.pmc_dirs))
+    copy_kib = (1 << 30) / 1024
+    cf = max(r["FETCH_SIZE"] for r in cfetch)
+    cw = max(r["WRITE_SIZE"] for r in cwrite)
+    fs, ws = copy_kib / cf, copy_kib / cw
+    f_kib, w_kib = mean(fetch, "FETCH_SIZE"), mean(write, "WRITE_SIZE")
+    out = {"kernel": "k_trace<false, false>", "workload": "terrain3.4M_1080p", "launches_measured": len(fetch),
+           "fetch_kib_per_launch_raw": f_kib, "write_kib_per_launch_raw": w_kib,
+           "copy_fetch_kib_raw": cf, "copy_write_kib_raw": cw, "fetch_scale": fs, "write_scale": ws,
+           "hbm_bytes_per_launch": (f_kib * fs + w_kib * ws) * 1024,
+           "valu_wave_instr_per_launch": mean(sq, "SQ_INSTS_VALU"),
+           "valu_lane_util": sum(r["SQ_THREAD_CYCLES_VALU"] for r in sq) /
+                             (64 * sum(r["SQ_ACTIVE_INST_VALU"] for r in sq)),
+           "sq_per_launch": {c: mean(sq, c) for c in sorted(sq[0])},
+           "sources": COUNTER_SOURCES, "sources_sha256": sources_sha256(COUNTER_SOURCES)}
+    with open(args.summarize_counters, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -385,8 +499,20 @@ def main():
                     help="frames rendered concurrently on their own streams (1: strictly one after another)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM traffic counters)")
+    ap.add_argument("--dump-signature", default=None,
+                    help="write the ray-tree signature of a seeded sample of the frame's paths to this .npz")
+    ap.add_argument("--dump-paths", type=int, default=1 << 17)
+    ap.add_argument("--dump-seed", type=int, default=17)
+    ap.add_argument("--summarize-counters", default=None,
+                    help="read rocprofv3 counter CSVs (--pmc-dirs) and write the traversal kernel's figures to "
+                         "this JSON")
+    ap.add_argument("--pmc-dirs", nargs="*", default=[],
+                    help="with --summarize-counters: directories of the FETCH_SIZE, WRITE_SIZE, copy FETCH_SIZE, "
+                         "copy WRITE_SIZE and SQ runs, in that order")
     args = ap.parse_args()
 
+    if args.summarize_counters:
+        return summarize_counters(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU: the render path has no multi-GPU "
                                    "mode (each GPU would render its own tiles with no exchange)", "n_gpus": args.gpus}))
@@ -488,6 +614,15 @@ def main():
     log(f"[bench] warmup done ({args.warmup} frames)")
     single_ms = run_frames(args.steps, 1) / args.steps  # one stream, no timer: frames back to back
     log(f"[bench] one frame in flight: {single_ms:.3f} ms/frame")
+    # isolated launches: the same frames one at a time with a HIP event pair around every launch, so each
+    # kernel's duration is its own (the roofline figures use these)
+    timer_iso = Timer()
+    run_frames(args.steps, 1, timer=timer_iso.handle)
+    iso = timer_iso.read()
+    timer_iso.close()
+    log(f"[bench] isolated launches: trace {iso['trace'][0] / args.steps:.3f} ms/frame over "
+        f"{iso['trace'][1] // args.steps} launches, shade {iso['shade'][0] / args.steps:.3f}, "
+        f"resolve {iso['resolve'][0] / args.steps:.3f}")
 
     timer = Timer()
     frame_ms = []
@@ -566,12 +701,49 @@ def main():
             f"{e2e['anaglyph_rgba8']:.3f} ms/frame over {e2e_frames} frames")
     e2e_best = e2e.get("memcpy")  # the library's default readback
 
-    # the dominant kernel is the fused traversal (closest-hit rays of depth d + shadow rays of depth d-1)
-    trace_total_ms, trace_launches = stages["trace"]
-    launches_per_frame = trace_launches / args.steps
+    # The dominant kernel is the fused traversal (closest-hit rays of depth d + shadow rays of depth d-1).
+    # It is not bound by HBM: its scene (247 MB) sits in the Infinity Cache and the measured DRAM traffic is
+    # a small fraction of the algorithmic bytes.  Its roofline is the VALU: algorithmic lane operations per
+    # launch over the isolated launch time, against 39.3 T lane operations/s.
+    iso_trace_ms, iso_launches = iso["trace"]
+    launches_per_frame = iso_launches / args.steps
+    avg_launch_ms = iso_trace_ms / iso_launches
+    ops_frame = OPS_PER_NODE_VISIT * int(cnt[3] + cnt[5]) + OPS_PER_TRI_TEST * int(cnt[4] + cnt[6])
+    ops_per_launch = ops_frame / launches_per_frame
+    achieved = ops_per_launch / (avg_launch_ms * 1e-3) / 1e12
     bytes_per_launch = (closest_bytes + any_bytes) / launches_per_frame
-    avg_launch_ms = trace_total_ms / trace_launches
-    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    stored = stored_counters(args.workload)
+    traffic = stored["hbm_bytes_per_launch"] if stored else None
+    copy_gbs = copy_peak_gbs(dev)
+    trace_s_frame = iso_trace_ms / args.steps * 1e-3
+    valu = None
+    if stored:
+        wave_instr_frame = stored["valu_wave_instr_per_launch"] * launches_per_frame
+        issue = wave_instr_frame * 4 / (1024 * 2.4e9) / trace_s_frame
+        valu = {"source": "stored rocprofv3 counters (profiles/k_trace_%s_counters.json)" % args.workload,
+                "wave_instr_per_frame": wave_instr_frame, "lane_util": stored["valu_lane_util"],
+                "issue_frac": issue, "lane_ops_frac": issue * stored["valu_lane_util"],
+                "lane_ops_per_node_visit": wave_instr_frame * 64 * stored["valu_lane_util"] / max(1, int(cnt[3] + cnt[5]))}
+    roofline = {
+        "bound": "alu", "kernel": "k_trace",
+        "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS,
+        "traffic": traffic,
+        "ops_per_launch": ops_per_launch, "ops_per_unit": {"node_visit": OPS_PER_NODE_VISIT,
+                                                           "triangle_test": OPS_PER_TRI_TEST},
+        "avg_launch_ms": avg_launch_ms, "launches_per_frame": launches_per_frame,
+        "timing": "HIP events around each launch on its stream, frames one at a time (isolated launches)",
+        "valu": valu,
+        "memory": {"algorithmic_bytes_per_launch": bytes_per_launch, "node_visit_bytes": node_visit,
+                   "algorithmic_gbs": bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9,
+                   "dram_bytes_per_launch": traffic,
+                   "dram_gbs": traffic / (avg_launch_ms * 1e-3) / 1e9 if traffic else None,
+                   "dram_frac_of_peak": traffic / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
+                   "hbm_peak_gbs": HBM_PEAK_GBS, "copy_peak_gbs": copy_gbs,
+                   "note": "algorithmic bytes count every node visit as a fetch; most are served by LDS, L2 and "
+                           "the Infinity Cache, so they are not quoted against the HBM peak"},
+    }
+    log(f"[bench] k_trace: {achieved:.2f} T algorithmic lane-ops/s = {achieved / VALU_PEAK_TOPS:.3f} of the VALU "
+        f"peak; copy kernel {copy_gbs:.0f} GB/s")
 
     res = {
         "metric": METRIC,
@@ -594,20 +766,45 @@ def main():
         "rays_per_frame": rays,
         "ray_counts": {"primary": int(cnt[0]), "mirror": int(cnt[1]), "shadow": int(cnt[2])},
         "stage_ms_per_frame": {k: v[0] / args.steps for k, v in stages.items() if v[1]},
+        "stage_ms_per_frame_isolated": {k: v[0] / args.steps for k, v in iso.items() if v[1]},
+        "work_per_frame": {"closest_node_visits": int(cnt[3]), "closest_tri_tests": int(cnt[4]),
+                           "shadow_node_visits": int(cnt[5]), "shadow_tri_tests": int(cnt[6])},
         "build_ms": build_ms,
-        "roofline": {
-            "bound": "hbm", "kernel": "k_trace",
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload),
-            "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms,
-            "launches_per_frame": launches_per_frame, "node_visit_bytes": node_visit,
-            "bytes_per_frame": {"closest": int(closest_bytes), "shadow": int(any_bytes)},
-        },
+        "roofline": roofline,
     }
+    need_ids = (not args.no_cpu_baseline) or args.dump_signature
+    if need_ids:
+        # one frame with ray-tree signatures; the kernels timed above write the same image
+        out_ids = render_stereo(gs, cam, path_ids=True)
+        plain = render_stereo(gs, cam)
+        torch.cuda.synchronize()
+        same = all(torch.equal(out_ids[k], plain[k]) for k in ("radiance", "hit_t", "hit_prim"))
+        del plain
+        from tests.parity import gpu_flat
+        g_ids = gpu_flat(out_ids)
+        del out_ids
+        if args.dump_signature:
+            import scenegen as sg
+            samp = sg.sample_paths(cam, args.dump_paths, seed=args.dump_seed)
+            np.savez(args.dump_signature, digest=sg.digest(scene, cam), samples=samp, workload=args.workload,
+                     seed=args.dump_seed, **{k: g_ids[k][samp] for k in g_ids})
+            log(f"[bench] wrote the signature of {len(samp)} sampled paths to {args.dump_signature}")
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a host sample ...")
-        res["cpu_baseline"] = cpu_baseline(scene, cam)
-        log(f"[bench] cpu baseline {res['cpu_baseline']['value']:.4f} Mrays/s on {res['cpu_baseline']['cores']} threads")
+        res["cpu_baseline"], orc = cpu_baseline(scene, cam, rays)
+        cb = res["cpu_baseline"]
+        log(f"[bench] cpu baseline {cb['value']:.5f} Mrays/s on {cb['cores']} threads (host nproc "
+            f"{cb['host_nproc']}), {cb['one_thread']['value']:.5f} Mrays/s on 1 thread; a full frame would take "
+            f"{cb['frame_seconds']:.0f} s (extrapolated)")
+        from tests.parity import compare
+        pr = compare(g_ids, orc, allow_min_one=False)
+        res["parity"] = {"n": pr["n"], "ties": pr["ties"], "tie_rate_upper95": pr["tie_rate_upper95"],
+                         "uncertified": len(pr["uncertified"]), "max_err": pr["max_err"],
+                         "max_rel_t_err": pr.get("max_rel_t_err"), "passed": pr["passed"],
+                         "timed_kernels_equal": same,
+                         "sample": "the cpu_baseline sample: GPU frame with ray-tree signatures vs the FP64 oracle"}
+        log(f"[bench] parity on {pr['n']} paths: ties {pr['ties']} (95% bound {pr['tie_rate_upper95']:.2e}), "
+            f"max radiance error {pr['max_err']:.2e}, timed kernels equal: {same}")
     timer.close()
     gs.close()
     print(json.dumps(res), flush=True)

@@ -7,7 +7,7 @@
  * ("parallel level 1") and the pixels inside each channel ("parallel level 2")
  * are independent, so both eyes are rendered by one pass over one ray queue.
  * The paper's Table 1 singles out BVH trees as fast to build and GPU-friendly;
- * scenes are accelerated by a linear BVH built on the device.  The paper
+ * scenes are accelerated by a BVH built on the device from the Morton order.  The paper
  * reports that up to 40% of its synthesis time goes to CPU-GPU transfer, so the
  * scene stays resident and the images are read back asynchronously.
  *
@@ -84,11 +84,17 @@ typedef struct {
 } rt_light;
 
 enum {
-  RT_ACCEL_LBVH = 0u,        /* triangles through a BVH built from the Morton order by locally-ordered
-                                clustering (default) */
-  RT_ACCEL_NONE = 1u,        /* brute force: every triangle is tested for every ray */
-  RT_ACCEL_LBVH_KARRAS = 2u  /* the same BVH layout with the binary tree from Karras (2012) emission over
-                                the Morton order and a bottom-up box refit */
+  RT_ACCEL_PLOC = 0u,   /* default: triangles through a 4-wide BVH whose binary tree comes from
+                           locally-ordered clustering over the Morton order (Meister and Bittner 2018),
+                           cut into 4-wide nodes by a surface-area cost table.  If that tree is too deep
+                           for the traversal stack (a long chain of nested boxes can make it so), the
+                           build falls back to RT_ACCEL_KARRAS and rt_scene_info.builder says so */
+  RT_ACCEL_NONE = 1u,   /* brute force: every triangle is tested for every ray */
+  RT_ACCEL_KARRAS = 2u, /* the linear BVH proper: binary tree from Karras (2012) emission over the sorted
+                           Morton codes and a bottom-up box refit (no SAH), same 4-wide layout */
+  /* earlier names of the same values */
+  RT_ACCEL_LBVH = RT_ACCEL_PLOC,
+  RT_ACCEL_LBVH_KARRAS = RT_ACCEL_KARRAS
 };
 
 typedef struct {
@@ -144,6 +150,9 @@ typedef struct {
   int64_t num_nodes;     /* BVH nodes (node_bytes / num_nodes bytes each) */
   int64_t node_bytes, triangle_bytes;
   float bounds_lo[3], bounds_hi[3];
+  int32_t builder;       /* RT_ACCEL_* that built the tree (RT_ACCEL_KARRAS after a fallback; RT_ACCEL_NONE
+                            without a tree) */
+  int32_t reserved;
 } rt_scene_info;
 
 rt_status rt_scene_get_info(rt_scene scene, rt_scene_info* info);

@@ -122,7 +122,7 @@ rt_status validate_desc(const rt_scene_desc* d) {
     return fail(RT_ERR_INVALID_ARGUMENT, "num_materials %d out of range [1, %d]", d->num_materials, RT_MAX_MATERIALS);
   if (d->num_lights < 0 || d->num_lights > RT_MAX_LIGHTS)
     return fail(RT_ERR_INVALID_ARGUMENT, "num_lights %d out of range [0, %d]", d->num_lights, RT_MAX_LIGHTS);
-  if (d->flags != RT_ACCEL_LBVH && d->flags != RT_ACCEL_NONE && d->flags != RT_ACCEL_LBVH_KARRAS)
+  if (d->flags != RT_ACCEL_PLOC && d->flags != RT_ACCEL_NONE && d->flags != RT_ACCEL_KARRAS)
     return fail(RT_ERR_INVALID_ARGUMENT, "unknown scene flags 0x%x", d->flags);
   if (!finite3(d->ambient) || !finite3(d->background))
     return fail(RT_ERR_INVALID_ARGUMENT, "ambient and background must be finite");
@@ -190,22 +190,26 @@ int64_t total_paths(const rt_stereo_camera* c) {
 constexpr int64_t kMinChunk = 32 * srt::kPathsPerTile;
 constexpr int64_t kMaxChunk = int64_t(1) << 25;
 
-// Largest pass size (multiple of a tile pair) whose workspace fits `bytes`.
-int64_t chunk_for(int64_t total, int32_t L, size_t bytes, srt::RenderPlan* plan) {
+// Largest pass size (multiple of a tile pair) whose workspace fits `bytes`.  stack_entries / stack_threads
+// size the traversal-stack spill area (0: the most any accepted tree and grid can need).
+int64_t chunk_for(int64_t total, int32_t L, size_t bytes, srt::RenderPlan* plan, int stack_entries = 0,
+                  int stack_threads = 0) {
   const int64_t cap = std::max<int64_t>(kMinChunk, std::min(kMaxChunk, current_tuning().max_pass_paths));
   int64_t hi_tiles = std::max<int64_t>(1, std::min(total, cap) / srt::kPathsPerTile);
   int64_t lo_tiles = std::min<int64_t>(kMinChunk / srt::kPathsPerTile, hi_tiles);
-  if (srt::plan_render(lo_tiles * srt::kPathsPerTile, L, 0, plan) > bytes) return 0;
+  auto need = [&](int64_t tiles) {
+    return srt::plan_render(tiles * srt::kPathsPerTile, L, 0, plan, stack_entries, stack_threads);
+  };
+  if (need(lo_tiles) > bytes) return 0;
   while (lo_tiles < hi_tiles) {
     int64_t mid = (lo_tiles + hi_tiles + 1) / 2;
-    if (srt::plan_render(mid * srt::kPathsPerTile, L, 0, plan) <= bytes)
+    if (need(mid) <= bytes)
       lo_tiles = mid;
     else
       hi_tiles = mid - 1;
   }
-  int64_t chunk = lo_tiles * srt::kPathsPerTile;
-  srt::plan_render(chunk, L, 0, plan);
-  return chunk;
+  need(lo_tiles);
+  return lo_tiles * srt::kPathsPerTile;
 }
 
 bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
@@ -271,32 +275,39 @@ rt_status readback(const rt_stereo_camera* cam, const rt_stereo_output* out, uin
   return RT_OK;
 }
 
+srt::BuildPlan plan_for(const rt_scene_desc* d, bool ploc) {
+  return srt::plan_build(d->num_triangles, d->num_spheres, d->num_planes, d->num_materials, d->num_lights,
+                         d->flags != RT_ACCEL_NONE, ploc);
+}
+
+// The traversal stack holds at most (width - 1) entries per level of the tree.
+bool stack_fits(int32_t depth) { return (srt::kNodeWidth - 1) * depth < srt::kStackMax; }
+
+rt_status build_status(const srt::BuildResult& res) {
+  if (res.status_bits & 1u)
+    return fail(RT_ERR_INVALID_ARGUMENT, "a triangle vertex is not finite or exceeds %g in magnitude", RT_MAX_COORD);
+  if (res.status_bits & 2u) return fail(RT_ERR_INVALID_ARGUMENT, "a triangle material index is out of range");
+  if (res.status_bits & 4u)
+    return fail(RT_ERR_INVALID_ARGUMENT, "a sphere is not finite, has radius <= 0 or a material out of range");
+  if (res.status_bits & 8u)
+    return fail(RT_ERR_INVALID_ARGUMENT, "a plane is not finite, has a zero normal or a material out of range");
+  if (res.status_bits & 16u) return fail(RT_ERR_DEVICE, "internal error: inconsistent BVH hierarchy");
+  return RT_OK;
+}
+
 rt_status current_device(int* dev) {
   hipError_t e = hipGetDevice(dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   return RT_OK;
 }
 
-rt_status render_one(const rt_scene_s* scene, const rt_stereo_camera* cam, const rt_stereo_output* out, char* ws,
-                     size_t ws_bytes, uint32_t flags, hipStream_t stream, hipStream_t copy_stream,
-                     srt::TimerImpl* timer) {
+// Renders the frame in passes of `chunk` paths with the workspace laid out by `plan`.
+rt_status render_passes(const rt_scene_s* scene, const rt_stereo_camera* cam, const rt_stereo_output* out, char* ws,
+                        const srt::RenderPlan& plan, int64_t chunk, uint32_t flags, hipStream_t stream,
+                        hipStream_t copy_stream, srt::TimerImpl* timer) {
   const int64_t total = total_paths(cam);
-  srt::RenderPlan plan;
-  const int64_t chunk = chunk_for(total, scene->dev.L, ws_bytes, &plan);
-  if (chunk == 0) {
-    size_t need = 0;
-    rt_render_workspace_min(scene->dev.L, &need);
-    return fail(RT_ERR_BUFFER_TOO_SMALL, "workspace of %zu bytes is below the minimum of %zu bytes", ws_bytes, need);
-  }
-  int dev = 0;
-  rt_status st = current_device(&dev);
-  if (st != RT_OK) return st;
-  if (dev != scene->device)
-    return fail(RT_ERR_INVALID_ARGUMENT, "scene was built on device %d, current device is %d", scene->device, dev);
-  const rt_tuning tune = current_tuning();
-  plan.grid_trace = srt::trace_grid_size(dev, tune.trace_blocks_per_cu, false);
   srt::RenderArgs ra{};
-  ra.stream_blocks = tune.stream_blocks;
+  ra.stream_blocks = current_tuning().stream_blocks;
   ra.one.sc = scene->dev;
   ra.one.cam = make_dev_camera(cam);
   ra.one.out = dev_outputs(out, flags);
@@ -316,6 +327,31 @@ rt_status render_one(const rt_scene_s* scene, const rt_stereo_camera* cam, const
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
   return readback(cam, out, flags, stream, copy_stream, timer);
+}
+
+rt_status check_scene_device(const rt_scene_s* scene, int* dev) {
+  rt_status st = current_device(dev);
+  if (st != RT_OK) return st;
+  if (*dev != scene->device)
+    return fail(RT_ERR_INVALID_ARGUMENT, "scene was built on device %d, current device is %d", scene->device, *dev);
+  return RT_OK;
+}
+
+rt_status render_one(const rt_scene_s* scene, const rt_stereo_camera* cam, const rt_stereo_output* out, char* ws,
+                     size_t ws_bytes, uint32_t flags, hipStream_t stream, hipStream_t copy_stream,
+                     srt::TimerImpl* timer) {
+  srt::RenderPlan plan;
+  const int64_t chunk = chunk_for(total_paths(cam), scene->dev.L, ws_bytes, &plan);
+  if (chunk == 0) {
+    size_t need = 0;
+    rt_render_workspace_min(scene->dev.L, &need);
+    return fail(RT_ERR_BUFFER_TOO_SMALL, "workspace of %zu bytes is below the minimum of %zu bytes", ws_bytes, need);
+  }
+  int dev = 0;
+  rt_status st = check_scene_device(scene, &dev);
+  if (st != RT_OK) return st;
+  plan.grid_trace = srt::trace_grid_size(dev, current_tuning().trace_blocks_per_cu, false);
+  return render_passes(scene, cam, out, ws, plan, chunk, flags, stream, copy_stream, timer);
 }
 
 size_t batch_table_bytes(int32_t n) { return (size_t(n) * sizeof(srt::DevItem) + 255) & ~size_t(255); }
@@ -416,10 +452,11 @@ rt_status rt_scene_storage_size(const rt_scene_desc* desc, size_t* storage_bytes
   rt_status s = validate_desc(desc);
   if (s != RT_OK) return s;
   if (!storage_bytes || !scratch_bytes) return fail(RT_ERR_INVALID_ARGUMENT, "size outputs are NULL");
-  srt::BuildPlan p = srt::plan_build(desc->num_triangles, desc->num_spheres, desc->num_planes, desc->num_materials,
-                                     desc->num_lights, desc->flags != RT_ACCEL_NONE, desc->flags == RT_ACCEL_LBVH);
+  const srt::BuildPlan p = plan_for(desc, desc->flags == RT_ACCEL_PLOC);
   *storage_bytes = p.storage_bytes;
   *scratch_bytes = p.scratch_bytes;
+  if (desc->flags == RT_ACCEL_PLOC)  // room for the fallback build as well
+    *scratch_bytes = std::max(*scratch_bytes, plan_for(desc, false).scratch_bytes);
   return ok();
 }
 
@@ -443,8 +480,7 @@ rt_status rt_scene_build(const rt_scene_desc* desc, void* storage, size_t storag
   for (int i = 0; i < desc->num_lights; ++i)
     if (!finite3(desc->lights[i].position) || !finite3(desc->lights[i].intensity))
       return fail(RT_ERR_INVALID_ARGUMENT, "light %d is not finite", i);
-  srt::BuildPlan plan = srt::plan_build(desc->num_triangles, desc->num_spheres, desc->num_planes, desc->num_materials,
-                                        desc->num_lights, desc->flags != RT_ACCEL_NONE, desc->flags == RT_ACCEL_LBVH);
+  srt::BuildPlan plan = plan_for(desc, desc->flags == RT_ACCEL_PLOC);
   if (!storage || !scratch) return fail(RT_ERR_INVALID_ARGUMENT, "storage and scratch must be device pointers");
   if (!aligned256(storage) || !aligned256(scratch))
     return fail(RT_ERR_INVALID_ARGUMENT, "storage and scratch must be 256-byte aligned");
@@ -459,17 +495,23 @@ rt_status rt_scene_build(const rt_scene_desc* desc, void* storage, size_t storag
   char* st = static_cast<char*>(storage);
   e = srt::build_scene_device(desc, plan, st, static_cast<char*>(scratch), static_cast<hipStream_t>(stream), &res);
   if (e != hipSuccess) return hip_fail(e, "scene build");
-  if (res.status_bits & 1u)
-    return fail(RT_ERR_INVALID_ARGUMENT, "a triangle vertex is not finite or exceeds %g in magnitude", RT_MAX_COORD);
-  if (res.status_bits & 2u) return fail(RT_ERR_INVALID_ARGUMENT, "a triangle material index is out of range");
-  if (res.status_bits & 4u)
-    return fail(RT_ERR_INVALID_ARGUMENT, "a sphere is not finite, has radius <= 0 or a material out of range");
-  if (res.status_bits & 8u)
-    return fail(RT_ERR_INVALID_ARGUMENT, "a plane is not finite, has a zero normal or a material out of range");
-  if (res.status_bits & 16u) return fail(RT_ERR_DEVICE, "internal error: inconsistent BVH hierarchy");
-  // the traversal stack holds at most (width - 1) entries per level of the tree
-  if ((srt::kNodeWidth - 1) * res.depth >= srt::kStackMax)
-    return fail(RT_ERR_UNSUPPORTED, "BVH depth %d exceeds the traversal stack", res.depth);
+  if ((s = build_status(res)) != RT_OK) return s;
+  int32_t builder = !plan.bvh ? int32_t(RT_ACCEL_NONE) : (plan.ploc ? int32_t(RT_ACCEL_PLOC) : int32_t(RT_ACCEL_KARRAS));
+  if (plan.bvh && plan.ploc && !stack_fits(res.depth)) {
+    // The clustering tree is too deep for the traversal stack: rebuild the same storage with the Karras
+    // tree, whose depth the Morton code bounds (its scratch is smaller than the clustering build's, and
+    // rt_scene_storage_size asks for the larger of the two).
+    const srt::BuildPlan kplan = plan_for(desc, false);
+    if (kplan.storage_bytes <= storage_bytes && kplan.scratch_bytes <= scratch_bytes) {
+      e = srt::build_scene_device(desc, kplan, st, static_cast<char*>(scratch), static_cast<hipStream_t>(stream),
+                                  &res);
+      if (e != hipSuccess) return hip_fail(e, "scene build (fallback tree)");
+      if ((s = build_status(res)) != RT_OK) return s;
+      plan = kplan;
+      builder = RT_ACCEL_KARRAS;
+    }
+  }
+  if (!stack_fits(res.depth)) return fail(RT_ERR_UNSUPPORTED, "BVH depth %d exceeds the traversal stack", res.depth);
 
   rt_scene_s* h = new (std::nothrow) rt_scene_s();
   if (!h) return fail(RT_ERR_DEVICE, "out of host memory");
@@ -502,6 +544,7 @@ rt_status rt_scene_build(const rt_scene_desc* desc, void* storage, size_t storag
   info.num_lights = desc->num_lights;
   info.num_materials = desc->num_materials;
   info.bvh_depth = plan.bvh ? res.depth : 0;
+  info.builder = builder;
   info.leaf_size = desc->num_triangles > 0 ? (plan.bvh ? srt::leaf_size() : 1) : 0;
   info.num_nodes = res.num_nodes;
   info.node_bytes = res.num_nodes * srt::kNodeBytes;

@@ -8,7 +8,7 @@
 //   4. stable LSD radix sort of (code, triangle id), 8 passes of 8 bits;
 //   5. binary tree over the sorted leaves: by default locally-ordered clustering
 //      (PLOC: neighbours in the Morton order merge by smallest surface area, so
-//      node boxes come with the merges); with RT_ACCEL_LBVH_KARRAS, Karras (2012)
+//      node boxes come with the merges); with RT_ACCEL_KARRAS, Karras (2012)
 //      emission (split at the highest differing bit; equal codes split by index) and
 //   6. a bottom-up box refit (an atomic arrival counter per node, the second
 //      child to arrive unions both boxes and climbs on);
@@ -31,6 +31,8 @@
 #include <vector>
 
 #include "rt_internal.h"
+#define SRT_HD __host__ __device__
+#include "ploc_rule.h"
 
 
 namespace srt {
@@ -547,13 +549,6 @@ __global__ __launch_bounds__(kBlock) void k_refit(const int2* __restrict__ child
 #endif
 constexpr int kPlocRadius = SRT_PLOC_RADIUS;
 
-__device__ inline float merged_area(float4 alo, float4 ahi, float4 blo, float4 bhi) {
-  const float dx = fmaxf(ahi.x, bhi.x) - fminf(alo.x, blo.x);
-  const float dy = fmaxf(ahi.y, bhi.y) - fminf(alo.y, blo.y);
-  const float dz = fmaxf(ahi.z, bhi.z) - fminf(alo.z, blo.z);
-  return dx * dy + dy * dz + dz * dx;
-}
-
 __global__ __launch_bounds__(kBlock) void k_ploc_init(const uint32_t* __restrict__ sorted_ids,
                                                       const float4* __restrict__ leaf_lo,
                                                       const float4* __restrict__ leaf_hi, int64_t n,
@@ -582,27 +577,8 @@ __global__ __launch_bounds__(kBlock) void k_ploc_nn(const float4* __restrict__ c
   __syncthreads();
   const int64_t i = start + threadIdx.x;
   if (i >= n) return;
-  const int si = threadIdx.x + kPlocRadius;
-  const float4 alo = s_lo[si], ahi = s_hi[si];
-  float best = INFINITY;
-  int32_t bj = int32_t(i > 0 ? i - 1 : i + 1);
-  for (int k = -kPlocRadius; k <= kPlocRadius; ++k) {  // ascending positions: ties keep the smaller one
-    const int64_t j = i + k;
-    if (k == 0 || j < 0 || j >= n) continue;
-    const float ar = merged_area(alo, ahi, s_lo[si + k], s_hi[si + k]);
-    if (ar < best) {
-      best = ar;
-      bj = int32_t(j);
-    }
-  }
-  // A merge that does not grow the box (coincident or nested boxes) prefers the parity partner i^1
-  // when it ties: runs of coincident triangles then pair up as (0,1), (2,3), ... and halve every
-  // round, instead of all choosing one cluster and merging one pair per round into a chain.
-  const int64_t partner = i ^ 1;
-  if (partner < n && best <= merged_area(alo, ahi, alo, ahi) &&
-      merged_area(alo, ahi, s_lo[si + int(partner - i)], s_hi[si + int(partner - i)]) == best)
-    bj = int32_t(partner);
-  nn[i] = bj;
+  // the LDS arrays hold positions start - R .. start + kBlock + R - 1
+  nn[i] = int32_t(ploc_partner(s_lo, s_hi, start - kPlocRadius, i, n, kPlocRadius));
 }
 
 __global__ __launch_bounds__(kBlock) void k_ploc_flags(const int32_t* __restrict__ nn, int64_t n,
@@ -1061,7 +1037,7 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
         int64_t n = T, next = T - 1;
         int cur = 0;
         for (int round = 0; n > 1; ++round) {
-          if (round > 100000) return hipErrorUnknown;  // every round merges at least one pair
+          if (round >= T) return hipErrorUnknown;  // every round merges at least one pair
           k_ploc_nn<<<blocks_for(n), kBlock, 0, stream>>>(c_lo[cur], c_hi[cur], n, nn);
           SRT_LAUNCH_CHECK();
           k_ploc_flags<<<blocks_for(n), kBlock, 0, stream>>>(nn, n, keep, merge);
@@ -1153,7 +1129,7 @@ hipError_t build_scene_device(const rt_scene_desc* desc, const BuildPlan& plan, 
         allocated += next_m;
         m = next_m;
         ++levels;
-        if (levels > 128 || allocated > T - 1) return hipErrorUnknown;  // impossible for a valid hierarchy
+        if (allocated > T - 1) return hipErrorUnknown;  // every level adds nodes: impossible for a valid hierarchy
       }
       result->num_nodes = allocated;
       depth = levels;

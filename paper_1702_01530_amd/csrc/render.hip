@@ -114,6 +114,7 @@ struct KArgs {
   float4* contrib[2];  // [cap][lstride]: the light's term times throughput
   uint8_t* vis[2];     // [cap][lstride]: 1 = light visible
   uint32_t* gstack;
+  int32_t gstack_entries; // spill entries per lane in gstack
   int64_t path_begin, path_count;
   uint32_t cap;           // entries per queue
   int32_t brute;
@@ -312,12 +313,13 @@ struct Stack {
   uint32_t* lds;     // &lds_stack[threadIdx.x], stride kBlock
   uint32_t* global;  // &gstack[global thread], stride gstride
   int gstride;
+  int gcap;          // spill entries per lane
   int sp;
   bool overflow;
 
   __device__ inline void push(int v) {
     if (sp >= kStackLds) {
-      if (sp - kStackLds >= kStackGlobal) {  // excluded by the build's depth check; never write out of bounds
+      if (sp - kStackLds >= gcap) {  // excluded by the depth checks on the host; never write out of bounds
         overflow = true;
         return;
       }
@@ -506,7 +508,7 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
   __shared__ float4 lnodes[kLdsNodes > 0 ? 4 * kLdsNodes : 1];
   const int lane = lane_id();
   const int gtid = blockIdx.x * kBlock + threadIdx.x;
-  Stack st{&lstack[threadIdx.x], a.gstack + gtid, a.trace_threads, 0, false};
+  Stack st{&lstack[threadIdx.x], a.gstack + gtid, a.trace_threads, a.gstack_entries, 0, false};
   const int LS = a.lstride;
   int kc = 0;  // nodes held in lnodes (the same for the whole block)
   if (!MULTI && kLdsNodes > 0 && a.one.sc.has_bvh && a.one.sc.T > 0 && !a.brute) {
@@ -924,7 +926,14 @@ int trace_grid_size(int device, int blocks_per_cu, bool multi) {
   return std::min(kMaxTraceBlocks, cached_cus[device] * per_cu);
 }
 
-size_t plan_render(int64_t chunk, int32_t L, int grid_trace, RenderPlan* p) {
+int spill_entries_for_depth(int32_t bvh_depth) {
+  // at most (width - 1) = 3 entries wait per level of the tree; the newest kStackLds stay in LDS
+  return std::min(kStackGlobal, std::max(1, 3 * bvh_depth - kStackLds + 1));
+}
+
+size_t plan_render(int64_t chunk, int32_t L, int grid_trace, RenderPlan* p, int stack_entries, int stack_threads) {
+  if (stack_entries <= 0 || stack_entries > kStackGlobal) stack_entries = kStackGlobal;
+  if (stack_threads <= 0) stack_threads = kMaxTraceBlocks * kBlock;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -947,7 +956,9 @@ size_t plan_render(int64_t chunk, int32_t L, int grid_trace, RenderPlan* p) {
     p->vis_off[k] = take(ns);
   }
   p->hit_off = take(n * 8);
-  p->gstack_off = take(size_t(kMaxTraceBlocks) * kBlock * kStackGlobal * 4);
+  p->stack_entries = stack_entries;
+  p->stack_threads = stack_threads;
+  p->gstack_off = take(size_t(stack_threads) * size_t(stack_entries) * 4);
   p->bytes = off;
   return off;
 }
@@ -982,6 +993,8 @@ hipError_t render_chunk(const RenderArgs& ra, hipStream_t s, TimerImpl* timer) {
   a.cap = uint32_t(p.chunk_paths);
   a.brute = (ra.flags & RT_FLAG_BRUTE_FORCE) ? 1 : 0;
   a.trace_threads = p.grid_trace * kBlock;
+  a.gstack_entries = p.stack_entries;
+  if (a.trace_threads > p.stack_threads) return hipErrorInvalidValue;  // the spill area is per grid thread
 
   const unsigned gtrace = unsigned(p.grid_trace);
   const unsigned gstream =

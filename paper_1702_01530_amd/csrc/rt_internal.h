@@ -159,13 +159,19 @@ struct RenderPlan {
   size_t counters_off, ro_off[2], rd_off[2], thr_off[2], hit_off, resinfo_off[2], srec_off[2], sowner_off[2],
       contrib_off[2], vis_off[2], gstack_off;
   size_t bytes;
-  int grid_trace;  // persistent workgroups for the traversal kernels
+  int grid_trace;     // persistent workgroups for the traversal kernels
+  int stack_entries;  // traversal-stack spill entries per lane
+  int stack_threads;  // traversal threads the spill area covers (at least grid_trace x 256)
 };
 
 // Persistent traversal workgroups: CUs x min(occupancy limit of the single or batch kernel,
 // blocks_per_cu if > 0).
 int trace_grid_size(int device, int blocks_per_cu, bool multi);
-size_t plan_render(int64_t chunk_paths, int32_t num_lights, int grid_trace, RenderPlan* plan);
+// stack_entries <= 0: the most any tree the build accepts needs; stack_threads <= 0: the largest grid.
+size_t plan_render(int64_t chunk_paths, int32_t num_lights, int grid_trace, RenderPlan* plan, int stack_entries = 0,
+                   int stack_threads = 0);
+// Spill entries per lane that a tree of this depth can need.
+int spill_entries_for_depth(int32_t bvh_depth);
 
 struct TimerImpl;
 void timer_begin(TimerImpl* t, int stage, hipStream_t s);

@@ -19,7 +19,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "stereort.h")
 RT_OK, RT_ERR_INVALID_ARGUMENT, RT_ERR_BUFFER_TOO_SMALL, RT_ERR_DEVICE, RT_ERR_UNSUPPORTED = range(5)
 STATUS_NAMES = {0: "RT_OK", 1: "RT_ERR_INVALID_ARGUMENT", 2: "RT_ERR_BUFFER_TOO_SMALL", 3: "RT_ERR_DEVICE",
                 4: "RT_ERR_UNSUPPORTED"}
-RT_ACCEL_LBVH, RT_ACCEL_NONE, RT_ACCEL_LBVH_KARRAS = 0, 1, 2
+RT_ACCEL_PLOC, RT_ACCEL_NONE, RT_ACCEL_KARRAS = 0, 1, 2
+RT_ACCEL_LBVH, RT_ACCEL_LBVH_KARRAS = RT_ACCEL_PLOC, RT_ACCEL_KARRAS  # earlier names
 RT_FLAG_PATH_IDS, RT_FLAG_COUNT_WORK, RT_FLAG_BRUTE_FORCE, RT_FLAG_READBACK_KERNEL = 1, 2, 4, 8
 RT_MAX_LIGHTS, RT_MAX_DEPTH = 8, 8
 RT_COMPOSE_ANAGLYPH_RED_CYAN, RT_COMPOSE_SIDE_BY_SIDE = 0, 1
@@ -60,7 +61,7 @@ class rt_scene_info(C.Structure):
         ("num_triangles", C.c_int64), ("num_spheres", C.c_int64), ("num_planes", C.c_int64),
         ("num_lights", C.c_int64), ("num_materials", C.c_int64), ("bvh_depth", C.c_int32), ("leaf_size", C.c_int32),
         ("num_nodes", C.c_int64), ("node_bytes", C.c_int64), ("triangle_bytes", C.c_int64),
-        ("bounds_lo", C.c_float * 3), ("bounds_hi", C.c_float * 3),
+        ("bounds_lo", C.c_float * 3), ("bounds_hi", C.c_float * 3), ("builder", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

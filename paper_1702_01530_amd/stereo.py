@@ -35,11 +35,15 @@ class GpuScene:
     triangles [T,3,3], tri_material [T], spheres [S,4], sphere_material [S], planes [P,4],
     plane_material [P], materials [M,10], lights [L,6], ambient [3], background [3]."""
 
-    ACCEL = {"lbvh": rt.RT_ACCEL_LBVH, "lbvh_karras": rt.RT_ACCEL_LBVH_KARRAS, "none": rt.RT_ACCEL_NONE}
+    ACCEL = {"ploc": rt.RT_ACCEL_PLOC, "karras": rt.RT_ACCEL_KARRAS, "none": rt.RT_ACCEL_NONE,
+             "lbvh": rt.RT_ACCEL_PLOC, "lbvh_karras": rt.RT_ACCEL_KARRAS}  # the last two: earlier names
+    BUILDERS = {rt.RT_ACCEL_PLOC: "ploc", rt.RT_ACCEL_KARRAS: "karras", rt.RT_ACCEL_NONE: "none"}
 
-    def __init__(self, scene, accel: str = "lbvh", device=None, stream=None):
-        """accel: "lbvh" (tree by clustering over the Morton order), "lbvh_karras" (Karras emission + refit)
-        or "none" (brute force)."""
+    def __init__(self, scene, accel: str = "ploc", device=None, stream=None):
+        """accel: "ploc" (binary tree by locally-ordered clustering over the Morton order, the default),
+        "karras" (the linear BVH: Karras emission over the Morton codes + refit) or "none" (brute force).
+        info()["builder"] names the builder that made the tree (a too-deep clustering tree falls back to
+        "karras")."""
         if accel not in self.ACCEL:
             raise ValueError(f"accel must be one of {sorted(self.ACCEL)}")
         self.device = torch.device(device or "cuda")
@@ -78,7 +82,9 @@ class GpuScene:
         self.num_triangles = d.num_triangles
 
     def info(self) -> dict:
-        return rt.rt_scene_get_info(self.handle)
+        out = rt.rt_scene_get_info(self.handle)
+        out["builder_name"] = self.BUILDERS.get(out["builder"], str(out["builder"]))
+        return out
 
     def close(self):
         if getattr(self, "handle", None):

@@ -502,3 +502,18 @@ def sample_paths(cam: StereoCamera, n: int, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
     n = min(int(n), total)
     return np.sort(rng.choice(total, size=n, replace=False)).astype(np.int64)
+
+
+def digest(scene: Scene, cam: StereoCamera) -> str:
+    """SHA-256 over a scene's arrays and a camera's fields: two runs (or two machines) that report the same
+    digest rendered the same input."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in (scene.triangles, scene.tri_material, scene.spheres, scene.sphere_material, scene.planes,
+              scene.plane_material, scene.materials, scene.lights, scene.ambient, scene.background):
+        h.update(np.ascontiguousarray(a).tobytes())
+    for v in (cam.center, cam.forward, cam.up):
+        h.update(np.asarray(v, np.float32).tobytes())
+    h.update(np.asarray([cam.hfov_deg, cam.baseline, cam.convergence], np.float32).tobytes())
+    h.update(np.asarray([cam.width, cam.height, cam.max_depth], np.int64).tobytes())
+    return h.hexdigest()

@@ -16,7 +16,6 @@ to it.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -44,24 +43,11 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def scene_digest(scene, cam) -> str:
-    """SHA-256 over the scene arrays and camera fields, so both sides can check they saw the same input."""
-    h = hashlib.sha256()
-    for a in (scene.triangles, scene.tri_material, scene.spheres, scene.sphere_material, scene.planes,
-              scene.plane_material, scene.materials, scene.lights, scene.ambient, scene.background):
-        h.update(np.ascontiguousarray(a).tobytes())
-    for v in (cam.center, cam.forward, cam.up):
-        h.update(np.asarray(v, np.float32).tobytes())
-    h.update(np.asarray([cam.hfov_deg, cam.baseline, cam.convergence], np.float32).tobytes())
-    h.update(np.asarray([cam.width, cam.height, cam.max_depth], np.int64).tobytes())
-    return h.hexdigest()
-
-
 def run_oracle(args):
     import oracle
     import scenegen as sg
     scene, cam = workload(args.workload)
-    digest = scene_digest(scene, cam)
+    digest = sg.digest(scene, cam)
     samples = sg.sample_paths(cam, args.paths, seed=args.seed)
     part = args.out + ".part.npz"
     done = {}

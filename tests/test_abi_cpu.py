@@ -54,14 +54,16 @@ def test_descriptor_validation(field, value, needle):
 
 
 def test_tree_builders_plan_their_own_scratch():
-    """Both tree builders are accepted; clustering needs more scratch than emission + refit, no more storage."""
+    """Both tree builders are accepted with the same storage.  The clustering build's scratch is the larger,
+    so a clustering tree too deep for the traversal stack can be rebuilt by emission + refit in place."""
     sizes = {}
-    for flags in (rt.RT_ACCEL_LBVH, rt.RT_ACCEL_LBVH_KARRAS, rt.RT_ACCEL_NONE):
+    for flags in (rt.RT_ACCEL_PLOC, rt.RT_ACCEL_KARRAS, rt.RT_ACCEL_NONE):
         d = _desc(T=100000)
         d.flags = flags
         sizes[flags] = rt.rt_scene_storage_size(d)
-    assert sizes[rt.RT_ACCEL_LBVH][0] == sizes[rt.RT_ACCEL_LBVH_KARRAS][0] > sizes[rt.RT_ACCEL_NONE][0]
-    assert sizes[rt.RT_ACCEL_LBVH][1] > sizes[rt.RT_ACCEL_LBVH_KARRAS][1] > sizes[rt.RT_ACCEL_NONE][1]
+    assert sizes[rt.RT_ACCEL_PLOC][0] == sizes[rt.RT_ACCEL_KARRAS][0] > sizes[rt.RT_ACCEL_NONE][0]
+    assert sizes[rt.RT_ACCEL_PLOC][1] > sizes[rt.RT_ACCEL_KARRAS][1] > sizes[rt.RT_ACCEL_NONE][1]
+    assert (rt.RT_ACCEL_LBVH, rt.RT_ACCEL_LBVH_KARRAS) == (rt.RT_ACCEL_PLOC, rt.RT_ACCEL_KARRAS)  # earlier names
 
 
 def test_build_rejects_bad_pointers_before_device_use():

@@ -28,7 +28,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-def render(torch, scene, cam, accel="lbvh", **kw):
+def render(torch, scene, cam, accel="ploc", **kw):
     from paper_1702_01530_amd.stereo import GpuScene, render_stereo
     gs = GpuScene(scene, accel=accel)
     out = render_stereo(gs, cam, path_ids=True, **kw)
@@ -36,7 +36,7 @@ def render(torch, scene, cam, accel="lbvh", **kw):
     return gs, out
 
 
-def check_parity(torch, scene, cam, samples=None, accel="lbvh", **kw):
+def check_parity(torch, scene, cam, samples=None, accel="ploc", **kw):
     say(f"[parity] {scene.name} {cam.width}x{cam.height} D={cam.max_depth} accel={accel} "
         f"samples={'all' if samples is None else len(samples)}")
     gs, out = render(torch, scene, cam, accel=accel)
@@ -65,9 +65,9 @@ def test_paper5_full_frame_lbvh_and_brute(torch_cuda):
 
 
 @pytest.mark.parametrize("grid,spheres,level,lights,depth,size,accel", [
-    (24, 4, 1, 2, 3, (96, 64), "lbvh"),
-    (40, 6, 2, 4, 4, (77, 45), "lbvh"),   # ragged tiles on both axes
-    (40, 6, 2, 4, 4, (77, 45), "lbvh_karras"),
+    (24, 4, 1, 2, 3, (96, 64), "ploc"),
+    (40, 6, 2, 4, 4, (77, 45), "ploc"),   # ragged tiles on both axes
+    (40, 6, 2, 4, 4, (77, 45), "karras"),
 ])
 def test_small_terrain_full_frame(torch_cuda, grid, spheres, level, lights, depth, size, accel):
     scene, cam = sg.make_small_terrain(seed=11 + grid, grid=grid, n_spheres=spheres, level=level, lights=lights,
@@ -131,6 +131,16 @@ def test_batch_equals_single_renders(torch_cuda):
         assert torch.equal(a["shadow_state"][..., :L], b["shadow_state"][..., :L]), i
     total = sum(int(o["ray_counts"][0]) for o in single)
     assert int(batched[0]["ray_counts"][0]) == total
+    # every item of the batch against the oracle, full frame (the batch kernels find each ray's item and
+    # scene per lane: this checks them against the definition, not only against single renders)
+    scenes = {id(g[0]): s1, id(g[1]): s2, id(g[2]): s3, id(g[3]): s4}
+    for i, (gs, cam) in enumerate(pairs):
+        b = dict(batched[i])
+        b["shadow_state"] = b["shadow_state"][..., :gs.num_lights]
+        res = compare(gpu_flat(b), oracle.render(scenes[id(gs)], cam))
+        say(f"[batch] item {i}: {cam.width}x{cam.height} D={cam.max_depth} ties={res['ties']} "
+            f"max_err={res['max_err']:.3g}")
+        assert_parity(res)
     # a workspace a little above the minimum: passes that straddle item boundaries
     need_min = rt.rt_render_workspace_min(4) + 4096
     multi = render_batch(pairs, path_ids=True, workspace=Workspace(need_min))
@@ -228,11 +238,20 @@ def test_served_results_equal_standalone_renders(torch_cuda):
     done = {q.rid: q for q in server.run(arrivals, timeout_s=120)}
     assert done[6].error and done[7].error  # unknown scene, invalid camera: failed alone
     assert server.batches >= 2
+    host_scenes = {"terrain": s1, "spheres": s2}
     for i, (sid, cam) in enumerate(specs[:6]):
         assert done[i].error is None, done[i].error
         alone = render_stereo(scenes[sid], cam, host=True)
         torch.cuda.synchronize()
         assert torch.equal(done[i].result["radiance"], alone["host_radiance"]), i
+        # the served image against the oracle: it equals the request's standalone render with ray-tree
+        # signatures byte for byte, and that render is compared with the oracle over the full frame
+        sig = render_stereo(scenes[sid], cam, path_ids=True)
+        torch.cuda.synchronize()
+        assert torch.equal(done[i].result["radiance"], sig["radiance"].cpu()), i
+        res = compare(gpu_flat(sig), oracle.render(host_scenes[sid], cam))
+        say(f"[serve] request {i}: {cam.width}x{cam.height} ties={res['ties']} max_err={res['max_err']:.3g}")
+        assert_parity(res)
     assert latency_stats(list(done.values()))["n"] == 6
     for g in scenes.values():
         g.close()
@@ -274,7 +293,7 @@ def test_degenerate_scenes(torch_cuda):
             check_parity(torch, scene, c, allow_min_one=False)
 
 
-@pytest.mark.parametrize("accel", ["lbvh", "lbvh_karras"])
+@pytest.mark.parametrize("accel", ["ploc", "karras"])
 def test_coincident_and_zero_area_triangles(torch_cuda, accel):
     """Hundreds of copies of one triangle (equal Morton codes, equal boxes, exact ties in t that only the
     smaller id decides), zero-area triangles (collinear and point-like: never hit) and a mirror floor."""
@@ -322,7 +341,7 @@ def test_maximum_lights_and_depth(torch_cuda):
     assert (orc["path_prims"][:, 8] >= 0).sum() > 1000  # most paths bounce to the last depth
 
 
-@pytest.mark.parametrize("accel", ["lbvh", "lbvh_karras"])
+@pytest.mark.parametrize("accel", ["ploc", "karras"])
 def test_flat_scene(torch_cuda, accel):
     """Every triangle in the plane y = 0 (boxes of zero height: the quantisation grid and the padding
     must still give every box a slab the rays can enter), a mirror stripe, grazing and axis-parallel
@@ -457,7 +476,7 @@ def _decode_children(rec: np.ndarray):
     return p[:, None] + qlo * step[:, None], p[:, None] + qhi * step[:, None], refs, valid
 
 
-@pytest.mark.parametrize("accel", ["lbvh", "lbvh_karras"])
+@pytest.mark.parametrize("accel", ["ploc", "karras"])
 def test_bvh_structure(torch_cuda, accel):
     """Reads the built tree back and walks it: every node is reached once, every triangle is in exactly
     one leaf, and every child's box (as the traversal sees it) contains the triangles under it."""
@@ -522,26 +541,53 @@ def terrain_3m():
     return sg.make_terrain_3m()
 
 
-@pytest.mark.parametrize("accel", ["lbvh", "lbvh_karras"])
+# Full-size parity.  The tie budget is 1e-4 of the paths with no minimum of one: at 16,384 sampled paths
+# at most one tie passes, and no ties bound the tie rate at 1.8e-4 (95%, Clopper-Pearson).  The oracle
+# tests every primitive for every query, so these take minutes of host time.
+HEADLINE_PATHS = 16384
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("accel", ["ploc", "karras"])
 def test_terrain212k_1080p_sampled(torch_cuda, terrain_212k, accel):
     scene, cam = terrain_212k
-    samples = sg.sample_paths(cam, 1024, seed=21)
-    check_parity(torch_cuda, scene, cam, samples=samples, accel=accel)
+    samples = sg.sample_paths(cam, HEADLINE_PATHS, seed=21)
+    _, _, res = check_parity(torch_cuda, scene, cam, samples=samples, accel=accel, allow_min_one=False)
+    say(f"[parity] tie rate upper bound (95%): {res['tie_rate_upper95']:.3g}")
 
 
+@pytest.mark.timeout(900)
 def test_terrain3m_1080p_sampled(torch_cuda, terrain_3m):
-    """The benchmark workload at its full size, in the launch configuration the benchmark times."""
+    """The benchmark workload at its full size, in the launch configuration the benchmark times.  The
+    kernels the benchmark times (no ray-tree signatures) give the same bytes as the checked render."""
+    torch = torch_cuda
+    from paper_1702_01530_amd.stereo import GpuScene, render_stereo
     scene, cam = terrain_3m
-    samples = sg.sample_paths(cam, 1024, seed=31)
-    check_parity(torch_cuda, scene, cam, samples=samples)
+    samples = sg.sample_paths(cam, HEADLINE_PATHS, seed=31)
+    say(f"[parity] {scene.name} {cam.width}x{cam.height} D={cam.max_depth} samples={len(samples)}")
+    gs = GpuScene(scene)
+    out = render_stereo(gs, cam, path_ids=True)
+    plain = render_stereo(gs, cam)
+    torch.cuda.synchronize()
+    assert int(out["ray_counts"][7]) == 0, "internal consistency check fired"
+    for k in ("radiance", "hit_t", "hit_prim"):
+        assert torch.equal(out[k], plain[k]), k
+    g = gpu_flat(out)
+    del out, plain
+    gs.close()
+    res = compare(g, oracle.render(scene, cam, samples=samples), allow_min_one=False)
+    say(f"[parity] ties={res['ties']} max_err={res['max_err']:.3g} t_err={res.get('max_rel_t_err', 0):.3g} "
+        f"tie rate upper bound (95%): {res['tie_rate_upper95']:.3g}")
+    assert_parity(res)
 
 
+@pytest.mark.timeout(900)
 def test_terrain3m_4k_sampled(torch_cuda, terrain_3m):
     """The 3.4M-triangle scene at 3840x2160 per eye (the roofline configuration), sampled paths."""
     scene, cam = terrain_3m
     cam = cam.resized(3840, 2160)
-    samples = sg.sample_paths(cam, 512, seed=41)
-    check_parity(torch_cuda, scene, cam, samples=samples)
+    samples = sg.sample_paths(cam, 4096, seed=41)
+    check_parity(torch_cuda, scene, cam, samples=samples, allow_min_one=False)
 
 
 def test_frames_in_flight_equal_single(torch_cuda, terrain_3m):
@@ -564,3 +610,59 @@ def test_frames_in_flight_equal_single(torch_cuda, terrain_3m):
             for name in ("radiance", "hit_t", "hit_prim"):
                 assert torch.equal(outs[k][name], ref[name]), (rep, k, name)
     gs.close()
+
+
+@pytest.mark.parametrize("accel", ["ploc", "karras"])
+def test_corner_boxes_and_grid_ties(torch_cuda, accel):
+    """Clusters whose merges tie exactly: a box B = [0,2]^3 (one triangle cutting its corner), tiny
+    triangles at B's low and high corners and a distant triangle, in that Morton order, so that every
+    merge with B or between the corners has B's area; copies at other places; a grid of equal quads.
+    The clustering rounds must still merge (a partner rule that broke mutual pairs here once refused
+    the scene)."""
+    base = [[[2, 0, 0], [0, 2, 0], [0, 0, 2]],
+            [[0, 0, 0], [0.01, 0, 0], [0, 0.01, 0.01]],
+            [[2, 2, 2], [1.99, 2, 2], [2, 1.99, 1.99]]]
+    tris = [[[-50, -50, -50], [-49, -50, -50], [-50, -49, -49]]]
+    for off in ((0, 0, 0), (4, 0, 1), (-4, 1, 3), (2, 3, 6)):
+        tris += [[[v[0] + off[0], v[1] + off[1], v[2] + off[2]] for v in t] for t in base]
+    for i in range(12):
+        for j in range(6):
+            x, z = -6.0 + i, 8.0 + j
+            tris += [[[x, -0.5, z], [x + 1, -0.5, z], [x + 1, -0.5, z + 1]], [[x, -0.5, z], [x + 1, -0.5, z + 1],
+                                                                            [x, -0.5, z + 1]]]
+    mats = [0] * (1 + 12) + [1] * (2 * 72)
+    scene = make_scene(tris=tris, tri_mat=mats, lights=[[1, 6, -2, 1, 1, 1], [-3, 4, 3, 0.5, 0.5, 0.5]],
+                       materials=[material(kd=(0.7, 0.5, 0.3), ks=(0.3, 0.3, 0.3)),
+                                  material(kd=(0.2, 0.3, 0.2), kr=(0.5, 0.5, 0.5))],
+                       ambient=(0.05,) * 3, name="corners")
+    cam = mono_camera(center=(1, 2.5, -6), forward=(0, -0.2, 1), width=64, height=40, depth=2, baseline=0.065,
+                      convergence=8.0)
+    g, _, _ = check_parity(torch_cuda, scene, cam, accel=accel, allow_min_one=False)
+    _, ob = render(torch_cuda, scene, cam, accel=accel, brute_force=True)
+    b = gpu_flat(ob)
+    for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state"):
+        assert np.array_equal(g[k], b[k]), k
+
+
+def test_deep_clustering_tree_falls_back_to_karras(torch_cuda):
+    """Nested triangles of growing size (boxes [0, 1.2^k]^3) make the clustering tree a chain as deep as
+    the input is long, too deep for the traversal stack: the build rebuilds with the Karras tree, says so,
+    and the render matches the oracle and the brute-force path."""
+    from paper_1702_01530_amd.stereo import GpuScene
+    tris, s = [], 1.0
+    for _ in range(200):
+        tris.append([[s, 0, 0], [0, s, 0], [0, 0, s]])
+        s *= 1.2
+    scene = make_scene(tris=tris, lights=[[3, 4, -2, 1, 1, 1]], materials=[material(kd=(0.6, 0.5, 0.4))],
+                       ambient=(0.05,) * 3, name="nested")
+    gs = GpuScene(scene, accel="ploc")
+    info = gs.info()
+    gs.close()
+    say(f"[nested] builder={info['builder_name']} depth={info['bvh_depth']}")
+    assert info["builder_name"] == "karras" and 3 * info["bvh_depth"] < 128
+    cam = mono_camera(center=(2, 2, -3), forward=(-0.1, -0.2, 1), width=48, height=32, depth=1)
+    g, _, _ = check_parity(torch_cuda, scene, cam, accel="ploc", allow_min_one=False)
+    _, ob = render(torch_cuda, scene, cam, accel="ploc", brute_force=True)
+    b = gpu_flat(ob)
+    for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state"):
+        assert np.array_equal(g[k], b[k]), k
