@@ -41,3 +41,17 @@ def mono_camera(center=(0, 1, 0), forward=(0, 0, 1), up=(0, 1, 0), width=64, hei
 
 def f32(x):
     return np.asarray(x, np.float32).astype(np.float64)
+
+
+def oracle_sampled(scene, cam, samples, chunk=2048, say=print):
+    """The oracle on a large sample of paths, in chunks with a progress line after each (a long oracle run
+    stays visibly alive); the result equals one call over the whole sample."""
+    import oracle
+    samples = np.asarray(samples, np.int64)
+    parts = []
+    for lo in range(0, len(samples), chunk):
+        parts.append(oracle.render(scene, cam, samples=samples[lo:lo + chunk]))
+        say(f"[oracle] {min(lo + chunk, len(samples))}/{len(samples)} paths")
+    out = {k: np.concatenate([p[k] for p in parts]) for k in parts[0] if k != "ray_counts"}
+    out["ray_counts"] = sum(p["ray_counts"] for p in parts)
+    return out

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import scenegen as sg
-from tests.helpers import make_scene, material, mono_camera, f32
+from tests.helpers import make_scene, material, mono_camera, f32, oracle_sampled
 from tests.parity import compare, assert_parity, gpu_flat
 
 pytestmark = pytest.mark.gpu
@@ -42,7 +42,7 @@ def check_parity(torch, scene, cam, samples=None, accel="ploc", **kw):
     gs, out = render(torch, scene, cam, accel=accel)
     assert int(out["ray_counts"][7]) == 0, "internal consistency check fired"
     g = gpu_flat(out)
-    orc = oracle.render(scene, cam, samples=samples)
+    orc = oracle.render(scene, cam) if samples is None else oracle_sampled(scene, cam, samples, say=say)
     res = compare(g, orc, **kw)
     say(f"[parity] ties={res['ties']} max_err={res['max_err']:.3g} t_err={res.get('max_rel_t_err', 0):.3g}")
     assert_parity(res)
@@ -575,7 +575,7 @@ def test_terrain3m_1080p_sampled(torch_cuda, terrain_3m):
     g = gpu_flat(out)
     del out, plain
     gs.close()
-    res = compare(g, oracle.render(scene, cam, samples=samples), allow_min_one=False)
+    res = compare(g, oracle_sampled(scene, cam, samples, say=say), allow_min_one=False)
     say(f"[parity] ties={res['ties']} max_err={res['max_err']:.3g} t_err={res.get('max_rel_t_err', 0):.3g} "
         f"tie rate upper bound (95%): {res['tie_rate_upper95']:.3g}")
     assert_parity(res)
