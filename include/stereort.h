@@ -231,6 +231,25 @@ rt_status rt_render_stereo(rt_scene scene, const rt_stereo_camera* camera, const
                            void* workspace, size_t workspace_bytes, uint32_t flags, void* stream,
                            void* copy_stream, rt_timer timer);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): rt_render_stereo with
+ * the library's own fixed device scratch as the workspace, so the caller
+ * passes only the scene, the camera and the outputs.  The scratch is a
+ * file-scope device array of RT_NOALLOC_SCRATCH_BYTES, one per GPU the library
+ * runs on, held until the process ends; the frame is rendered in as many
+ * passes over pixel tiles as it takes to fit (results are bitwise those of
+ * rt_render_stereo).  Nothing is allocated: no hipMalloc, hipFree or timer
+ * events.  Every call on one GPU uses that GPU's one array, so calls whose
+ * work overlaps on a GPU (on different streams, or from different threads
+ * without ordering) RACE and corrupt each other's results: order them on one
+ * stream or synchronise between them.  A scene whose smallest pass does not
+ * fit the scratch gives RT_ERR_BUFFER_TOO_SMALL (never for RT_MAX_LIGHTS
+ * lights and a tree the build accepts).  Asynchronous on `stream`; host
+ * readback as in rt_render_stereo. */
+#define RT_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+rt_status rt_render_stereo_noalloc(rt_scene scene, const rt_stereo_camera* camera, const rt_stereo_output* out,
+                                   uint32_t flags, void* stream, void* copy_stream);
+
 typedef struct {
   rt_scene scene;
   rt_stereo_camera camera;

@@ -442,6 +442,34 @@ struct rt_batch_graph_s {
   int64_t* ray_counts = nullptr;
 };
 
+// The fixed device scratch of rt_render_stereo_noalloc: one array per GPU the library runs on,
+// held until the process ends.  In host code `scratch` names a host-side stand-in, not device
+// memory; its device address on the current GPU comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) char scratch[RT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+std::vector<char*> g_scratch_ptr;  // per device ordinal; nullptr until looked up
+
+// The device address of `scratch` on device `dev` (the current device).
+rt_status scratch_on_device(int dev, char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (dev < 0) return fail(RT_ERR_DEVICE, "no current device");
+  if (size_t(dev) >= g_scratch_ptr.size()) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p || !aligned256(p)) return fail(RT_ERR_DEVICE, "the device scratch is not 256-byte aligned");
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return RT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* rt_last_error(void) { return g_error.c_str(); }
@@ -601,6 +629,33 @@ rt_status rt_render_stereo(rt_scene scene, const rt_stereo_camera* camera, const
                  static_cast<hipStream_t>(stream), static_cast<hipStream_t>(copy_stream), timer);
   if (s != RT_OK) return s;
   if (timer && timer->error != hipSuccess) return hip_fail(timer->error, "timer event");
+  return ok();
+}
+
+rt_status rt_render_stereo_noalloc(rt_scene scene, const rt_stereo_camera* camera, const rt_stereo_output* out,
+                                   uint32_t flags, void* stream, void* copy_stream) {
+  if (!scene) return fail(RT_ERR_INVALID_ARGUMENT, "scene is NULL");
+  rt_status s = validate_camera(camera);
+  if (s != RT_OK) return s;
+  if ((s = check_output(out, flags)) != RT_OK) return s;
+  if (flags & ~kKnownFlags) return fail(RT_ERR_INVALID_ARGUMENT, "unknown render flags 0x%x", flags);
+  int dev = 0;
+  if ((s = check_scene_device(scene, &dev)) != RT_OK) return s;
+  char* ws = nullptr;
+  if ((s = scratch_on_device(dev, &ws)) != RT_OK) return s;
+  // The spill area is sized to this scene's tree and the traversal grid actually launched, so the
+  // fixed scratch leaves the most room for the pass's queues.
+  srt::RenderPlan plan;
+  const int grid = srt::trace_grid_size(dev, current_tuning().trace_blocks_per_cu, false);
+  const int64_t chunk = chunk_for(total_paths(camera), scene->dev.L, RT_NOALLOC_SCRATCH_BYTES, &plan,
+                                  srt::spill_entries_for_depth(scene->info.bvh_depth), grid * srt::kTraceBlock);
+  if (chunk == 0)
+    return fail(RT_ERR_BUFFER_TOO_SMALL, "the smallest pass for %d lights and tree depth %d does not fit the %zu-byte "
+                "device scratch", scene->dev.L, scene->info.bvh_depth, size_t(RT_NOALLOC_SCRATCH_BYTES));
+  plan.grid_trace = grid;
+  s = render_passes(scene, camera, out, ws, plan, chunk, flags, static_cast<hipStream_t>(stream),
+                    static_cast<hipStream_t>(copy_stream), nullptr);
+  if (s != RT_OK) return s;
   return ok();
 }
 

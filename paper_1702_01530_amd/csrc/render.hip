@@ -36,7 +36,7 @@
 namespace srt {
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = kTraceBlock;
 constexpr int kWaves = kBlock / 64;
 constexpr int kStackLds = SRT_STACK_LDS;       // traversal stack entries per lane kept in LDS (power of two)
 constexpr int kStackGlobal = kStackMax - kStackLds;  // older entries spill to the workspace

@@ -51,6 +51,7 @@ constexpr int kMatFloat4 = 3;    // (kd, n), (ks, 0), (kr, 0)
 constexpr int kLightFloat4 = 2;  // (pos, 0), (I, 0)
 constexpr float kSecondaryTmin = 1e-4f;
 constexpr int kStackMax = 128;   // traversal stack entries per lane (LDS ring + spill area)
+constexpr int kTraceBlock = 256; // threads per traversal workgroup
 
 struct DevScene {
   const float4* nodes;

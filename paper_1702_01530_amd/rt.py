@@ -107,6 +107,8 @@ _SIGNATURES = {
     "rt_render_workspace_min": (C.c_int, [C.c_int32, C.POINTER(C.c_size_t)]),
     "rt_render_stereo": (C.c_int, [C.c_void_p, C.POINTER(rt_stereo_camera), C.POINTER(rt_stereo_output), C.c_void_p,
                                    C.c_size_t, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rt_render_stereo_noalloc": (C.c_int, [C.c_void_p, C.POINTER(rt_stereo_camera), C.POINTER(rt_stereo_output),
+                                           C.c_uint32, C.c_void_p, C.c_void_p]),
     "rt_render_batch_workspace_size": (C.c_int, [C.POINTER(rt_batch_item), C.c_int32, C.POINTER(C.c_size_t)]),
     "rt_render_batch": (C.c_int, [C.POINTER(rt_batch_item), C.c_int32, C.c_void_p, C.c_size_t, C.c_uint32,
                                   C.c_void_p, C.c_void_p]),
@@ -201,6 +203,10 @@ def rt_render_workspace_min(num_lights: int) -> int:
 def rt_render_stereo(handle, cam, out, ws_ptr, ws_bytes, flags, stream, copy_stream=None, timer=None):
     check(lib().rt_render_stereo(handle, C.byref(cam), C.byref(out), ws_ptr, ws_bytes, flags, stream, copy_stream,
                                  timer))
+
+
+def rt_render_stereo_noalloc(handle, cam, out, flags, stream, copy_stream=None):
+    check(lib().rt_render_stereo_noalloc(handle, C.byref(cam), C.byref(out), flags, stream, copy_stream))
 
 
 def rt_render_batch_workspace_size(items) -> int:
