@@ -222,7 +222,8 @@ def bench_batch(args):
 
 def bench_serve(args):
     """Serving: Poisson arrivals over 8 resident scenes (10k-2M triangles), 640x480 to 3840x2160, depth 1-4.
-    Continuous batching (3 in-flight batch slots) versus one request at a time, on the same arrival trace."""
+    Continuous batching (3 in-flight batch slots, batches grouped by cost class) versus one request at a time
+    and versus 3 slots with requests of any cost in one batch, on the same arrival trace."""
     import numpy as np
     import torch
     import scenegen as sg
@@ -233,7 +234,9 @@ def bench_serve(args):
     log(f"[serve] {len(trace)} requests at {args.rate:.0f}/s over {len(scenes)} scenes "
         f"({min(s.num_triangles for s in scenes)}-{max(s.num_triangles for s in scenes)} triangles)")
     out = {}
-    for name, slots, max_batch in (("continuous_batching", 3, 64), ("one_at_a_time", 1, 1)):
+    modes = (("continuous_batching", 3, 64, args.group_ratio), ("one_at_a_time", 1, 1, None),
+             ("continuous_ungrouped", 3, 64, None))
+    for name, slots, max_batch, group in modes:
         rend = GpuRenderer(gss, slots=slots, workspace_bytes=6 << 30)
         rend.prewarm(sorted({(c.width, c.height) for _, _, c in trace}), count=12)
 
@@ -242,14 +245,17 @@ def bench_serve(args):
                 rend.release(req.result["radiance"])
                 req.result = None
 
-        server = Server(rend, hbm_budget=48 << 30, max_batch_paths=1 << 25, max_batch=max_batch, on_complete=consume)
+        server = Server(rend, hbm_budget=48 << 30, max_batch_paths=1 << 25, max_batch=max_batch, on_complete=consume,
+                        group_ratio=group)
         server.run([(0.0, Request(-1 - i, k, cam)) for i, (_, k, cam) in enumerate(trace[:4])])  # warm-up
         torch.cuda.synchronize()
-        server = Server(rend, hbm_budget=48 << 30, max_batch_paths=1 << 25, max_batch=max_batch, on_complete=consume)
+        server = Server(rend, hbm_budget=48 << 30, max_batch_paths=1 << 25, max_batch=max_batch, on_complete=consume,
+                        group_ratio=group)
         done = server.run([(t, Request(i, k, cam)) for i, (t, k, cam) in enumerate(trace)])
         st = latency_stats(done)
         st["batches"] = server.batches
         st["mean_batch"] = float(np.mean(server.batch_sizes)) if server.batch_sizes else 0.0
+        st["slots"], st["group_ratio"] = slots, group
         out[name] = st
         log(f"[serve] {name}: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
             f"{st['stereo_fps']:.1f} stereo frames/s, {st['batches']} batches (mean {st['mean_batch']:.1f})")
@@ -259,7 +265,8 @@ def bench_serve(args):
            "value": out["continuous_batching"]["stereo_fps"], "unit": "stereo frames/s", "n_gpus": 1,
            "steps": args.requests, "warmup": 4, "ms_per_step": 1e3 / out["continuous_batching"]["stereo_fps"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "serve", "requests": args.requests, "rate_hz": args.rate, "scenes": len(scenes)},
+           "config": {"workload": "serve", "requests": args.requests, "rate_hz": args.rate, "scenes": len(scenes),
+                      "group_ratio": args.group_ratio},
            "p50_ms": out["continuous_batching"]["p50_ms"], "p99_ms": out["continuous_batching"]["p99_ms"],
            "modes": out}
     for g in gss.values():
@@ -494,6 +501,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=200, help="serving workload: number of requests")
     ap.add_argument("--rate", type=float, default=100.0, help="serving workload: Poisson arrival rate (1/s)")
+    ap.add_argument("--group-ratio", type=float, default=4.0,
+                    help="serving workload: a batch takes requests within this factor of its first request's cost")
     ap.add_argument("--no-end-to-end", action="store_true")
     ap.add_argument("--frames-in-flight", type=int, default=2,
                     help="frames rendered concurrently on their own streams (1: strictly one after another)")

@@ -58,6 +58,12 @@ class Renderer:
     def validate(self, req: Request) -> Optional[str]:  # error text for a request that cannot be rendered
         return None
 
+    def cost(self, req: Request) -> float:  # relative device work of the request (any unit)
+        return float(self.paths(req))
+
+    def reserved_bytes(self) -> int:  # device bytes the renderer holds for itself (not per request)
+        return 0
+
     def launch(self, slot: int, reqs: list) -> Any:  # enqueue the batch; returns a handle
         raise NotImplementedError
 
@@ -71,9 +77,14 @@ class Renderer:
 class Server:
     def __init__(self, renderer: Renderer, hbm_budget: int, max_batch_paths: int, max_batch: int = 64,
                  max_bypass: int = 4, clock: Callable[[], float] = time.perf_counter,
-                 on_complete: Optional[Callable[[Request], None]] = None):
+                 on_complete: Optional[Callable[[Request], None]] = None, group_ratio: Optional[float] = None):
         self.r = renderer
-        self.budget = int(hbm_budget)
+        self.budget = int(hbm_budget) - int(renderer.reserved_bytes())
+        if self.budget <= 0:
+            raise ValueError("the renderer's own device memory leaves no budget for requests")
+        if group_ratio is not None and group_ratio < 1.0:
+            raise ValueError("group_ratio must be >= 1")
+        self.group_ratio = group_ratio  # None: requests of any cost share a batch
         self.max_batch_paths = int(max_batch_paths)
         self.max_batch = int(max_batch)
         self.max_bypass = int(max_bypass)
@@ -168,11 +179,17 @@ class Server:
         head_fits = self.in_use + self.r.bytes_needed(head) <= self.budget
         may_bypass = head.bypassed < self.max_bypass
         kept = collections.deque()
+        lead_cost = None  # cost of the batch's first request (cost-class grouping)
         while self.waiting and len(batch) < self.max_batch:
             req = self.waiting.popleft()
             need = self.r.bytes_needed(req)
             fits = self.in_use + need <= self.budget and paths + self.r.paths(req) <= self.max_batch_paths
+            if fits and batch and self.group_ratio is not None:
+                c = self.r.cost(req)
+                fits = lead_cost / self.group_ratio <= c <= lead_cost * self.group_ratio
             if fits and (req is head or head_fits or may_bypass):
+                if not batch:
+                    lead_cost = self.r.cost(req)
                 batch.append(req)
                 paths += self.r.paths(req)
                 self.in_use += need
@@ -237,6 +254,16 @@ class GpuRenderer(Renderer):
     def paths(self, req: Request) -> int:
         tiles = -(-int(req.camera.width) // 8) * -(-int(req.camera.height) // 8)
         return 2 * 64 * tiles
+
+    def cost(self, req: Request) -> float:
+        """Relative device work: paths, weighted by the shadow rays (one per light) and the mirror bounces
+        a path can spawn."""
+        gs = self.scenes.get(req.scene_id)
+        lights = gs.num_lights if gs is not None else 0
+        return self.paths(req) * (1.0 + 0.5 * lights) * (1.0 + 0.15 * int(req.camera.max_depth))
+
+    def reserved_bytes(self) -> int:
+        return sum(ws.nbytes for ws in self.workspaces)
 
     def validate(self, req: Request) -> Optional[str]:
         if req.scene_id not in self.scenes:

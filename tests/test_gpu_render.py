@@ -220,9 +220,10 @@ def test_tuning_does_not_change_results(torch_cuda):
     g1.close()
 
 
-def test_served_results_equal_standalone_renders(torch_cuda):
-    """Requests served in a mix (continuous batching over two in-flight slots) give exactly the image
-    each request gets when rendered alone."""
+@pytest.mark.parametrize("group_ratio", [None, 2.0])
+def test_served_results_equal_standalone_renders(torch_cuda, group_ratio):
+    """Requests served in a mix (continuous batching over two in-flight slots, with and without cost-class
+    grouping) give exactly the image each request gets when rendered alone."""
     torch = torch_cuda
     from paper_1702_01530_amd.serve import GpuRenderer, Request, Server, latency_stats
     from paper_1702_01530_amd.stereo import GpuScene, render_stereo
@@ -230,7 +231,9 @@ def test_served_results_equal_standalone_renders(torch_cuda):
     s2, c2 = sg.make_spheres_scene()
     scenes = {"terrain": GpuScene(s1), "spheres": GpuScene(s2)}
     rend = GpuRenderer(scenes, slots=2, workspace_bytes=512 << 20)
-    server = Server(rend, hbm_budget=64 << 20, max_batch_paths=1 << 16, max_batch=4)
+    # the slots' workspaces come off the budget; 64 MiB are left for the requests' outputs
+    server = Server(rend, hbm_budget=rend.reserved_bytes() + (64 << 20), max_batch_paths=1 << 16, max_batch=4,
+                    group_ratio=group_ratio)
     specs = [("terrain", c1.resized(64, 40)), ("spheres", c2.resized(48, 48)), ("terrain", c1.resized(33, 17)),
              ("spheres", c2.resized(80, 60).with_(max_depth=0)), ("terrain", c1.resized(96, 64)),
              ("spheres", c2.resized(20, 90)), ("nope", c2), ("terrain", c1.with_(hfov_deg=200.0))]

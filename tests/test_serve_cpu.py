@@ -157,3 +157,47 @@ def test_run_plays_back_arrivals():
     arrivals = [(0.001 * i, Request(i, "a", 20)) for i in range(50)]
     done = s.run(arrivals)
     assert len(done) == 50 and all(q.latency >= 0 for q in done)
+
+
+def test_cost_classes_go_out_in_separate_batches():
+    """With group_ratio, a batch takes only requests within that factor of its first request's cost; the others
+    start in another free slot of the same step."""
+    clock = Clock()
+    r = FakeRenderer(clock, slots=3, per_path=1e-3)
+    s = Server(r, hbm_budget=10_000, max_batch_paths=1000, clock=clock, group_ratio=4.0)
+    for rid, size in enumerate((100, 10, 120, 8, 300, 20)):
+        s.submit(Request(rid, "a", size))
+    s.step()
+    batches = [ids for _, ids, _ in r.launched]
+    assert batches[0] == [0, 2, 4]          # costs 100, 120, 300: within 4x of the first request
+    assert batches[1] == [1, 3, 5]          # costs 10, 8, 20
+    drive(s, clock)
+    assert [q.error for q in s.completed] == [None] * 6
+    # without grouping everything shares one batch
+    clock2 = Clock()
+    r2 = FakeRenderer(clock2, slots=3)
+    s2 = Server(r2, hbm_budget=10_000, max_batch_paths=1000, clock=clock2)
+    for rid, size in enumerate((100, 10, 120, 8, 300, 20)):
+        s2.submit(Request(rid, "a", size))
+    s2.step()
+    assert [ids for _, ids, _ in r2.launched] == [[0, 1, 2, 3, 4, 5]]
+    with pytest.raises(ValueError):
+        Server(r2, hbm_budget=10_000, max_batch_paths=1000, clock=clock2, group_ratio=0.5)
+
+
+def test_renderer_memory_is_taken_off_the_budget():
+    clock = Clock()
+
+    class Reserving(FakeRenderer):
+        def reserved_bytes(self):
+            return 60
+
+    s = Server(Reserving(clock), hbm_budget=100, max_batch_paths=1000, clock=clock)
+    assert s.budget == 40
+    s.submit(Request(0, "a", 50))  # fits 100 but not the 40 left
+    assert s.completed[0].error and "budget" in s.completed[0].error
+    s.submit(Request(1, "a", 30))
+    drive(s, clock)
+    assert s.completed[1].error is None and s.peak_in_use <= 40
+    with pytest.raises(ValueError):
+        Server(Reserving(clock), hbm_budget=60, max_batch_paths=1000, clock=clock)
