@@ -233,7 +233,7 @@ __device__ inline float slab(float lox, float hix, float loy, float hiy, float l
 }
 
 // Entry distances of the four children of BVH4 node `node` (+inf where the ray misses the child's
-// box inside [tmin, tmax]) and their references.
+// box inside [tmin, tmax]; with HITS_ONLY 0 instead of the distance of a hit child) and their references.
 // Reads node `node` of the LDS array `lnodes`.  Written as LDS instructions because the compiler
 // merges two plain reads of the same shape from LDS and global memory into one flat read, which
 // takes the vector-memory path for every lane.
@@ -253,6 +253,7 @@ __device__ __attribute__((always_inline)) inline void lds_read_node(const float4
 }
 
 // Nodes below `kc` are read from the LDS copy `lnodes` of the top of the tree.
+template <bool HITS_ONLY>
 __device__ __attribute__((always_inline)) inline void node4_children(const float4* __restrict__ nodes,
                                                                      const float4* lnodes, int kc, int node,
                                                                      float3 inv, float3 oi, float tmin, float tmax,
@@ -284,7 +285,8 @@ __device__ __attribute__((always_inline)) inline void node4_children(const float
     const float zn = fmaf(float((nz >> (8 * k)) & 0xffu), az, bz), zf = fmaf(float((fz >> (8 * k)) & 0xffu), az, bz);
     const float tn = fmaxf(fmaxf(xn, yn), fmaxf(zn, tmin));
     const float tf = fminf(fminf(xf, yf), fminf(zf, tmax));
-    t[k] = tn <= tf ? tn : INFINITY;
+    // HITS_ONLY: 0 for a hit child, +inf otherwise (an occlusion query needs no entry distance)
+    t[k] = tn <= tf ? (HITS_ONLY ? 0.0f : tn) : INFINITY;
   }
   r[0] = __float_as_int(n1.x);
   r[1] = __float_as_int(n1.y);
@@ -297,6 +299,8 @@ __device__ __attribute__((always_inline)) inline void node4_children(const float
   t[1] = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, inv, oi, tmin, tmax);
   t[2] = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, inv, oi, tmin, tmax);
   t[3] = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, inv, oi, tmin, tmax);
+  if (HITS_ONLY)
+    for (int k = 0; k < 4; ++k) t[k] = t[k] < INFINITY ? 0.0f : INFINITY;
   r[0] = __float_as_int(cr.x);
   r[1] = __float_as_int(cr.y);
   r[2] = __float_as_int(cr.z);
@@ -440,14 +444,29 @@ __device__ inline void traverse(const DevScene& sc, const float4* lnodes, int kc
       const float tmax = limit();
       float t[4];
       int r[4];
-      node4_children(sc.nodes, lnodes, kc, node, inv, oi, tmin, tmax, t, r);
-      sort4(t, r);
-      if (t[0] < INFINITY) {
-        node = r[0];
-        const int np = int(t[1] < INFINITY) + int(t[2] < INFINITY) + int(t[3] < INFINITY);
-        if (np > 0) st.push_sorted(r[1], r[2], r[3], np);
+      node4_children<ANY>(sc.nodes, lnodes, kc, node, inv, oi, tmin, tmax, t, r);
+      if (ANY) {
+        // occlusion: the order of the hit children does not change the answer, so they are taken in
+        // slot order (the same for every lane of the wave) without sorting: the first hit child next,
+        // the later hit children pushed so that they pop in slot order
+        const bool h0 = t[0] == 0.0f, h1 = t[1] == 0.0f, h2 = t[2] == 0.0f, h3 = t[3] == 0.0f;
+        if (h0 || h1 || h2 || h3) {
+          node = h0 ? r[0] : (h1 ? r[1] : (h2 ? r[2] : r[3]));
+          const bool g1 = h1 && h0, g2 = h2 && (h0 || h1), g3 = h3 && (h0 || h1 || h2);  // hits after the first
+          const int np = int(g1) + int(g2) + int(g3);
+          if (np > 0) st.push_sorted(g1 ? r[1] : (g2 ? r[2] : r[3]), (g1 && g2) ? r[2] : r[3], r[3], np);
+        } else {
+          node = st.sp > 0 ? st.pop() : kDoneRef;
+        }
       } else {
-        node = st.sp > 0 ? st.pop() : kDoneRef;
+        sort4(t, r);
+        if (t[0] < INFINITY) {
+          node = r[0];
+          const int np = int(t[1] < INFINITY) + int(t[2] < INFINITY) + int(t[3] < INFINITY);
+          if (np > 0) st.push_sorted(r[1], r[2], r[3], np);
+        } else {
+          node = st.sp > 0 ? st.pop() : kDoneRef;
+        }
       }
     }
     if (node < 0) {
