@@ -633,14 +633,18 @@ def main():
         f"{iso['trace'][1] // args.steps} launches, shade {iso['shade'][0] / args.steps:.3f}, "
         f"resolve {iso['resolve'][0] / args.steps:.3f}")
 
+    # per-stage device time with F frames in flight (launches overlap): its own run, since the event pair
+    # around every launch costs time of its own
     timer = Timer()
+    run_frames(args.steps, F, timer=timer.handle)
+    stages = timer.read()
+    # the timed region: K frames, F in flight, no per-launch events
     frame_ms = []
     t_wall = time.perf_counter()
-    total_ms = run_frames(args.steps, F, timer=timer.handle, per_frame=frame_ms)
+    total_ms = run_frames(args.steps, F, per_frame=frame_ms)
     wall_s = time.perf_counter() - t_wall
     per_frame = [a.elapsed_time(b) for a, b in frame_ms]
     ms_per_step = total_ms / args.steps
-    stages = timer.read()
     log(f"[bench] timed {args.steps} frames, {F} in flight: {ms_per_step:.3f} ms/frame "
         f"(frame latency median {np.median(per_frame):.3f} ms), wall {wall_s:.2f} s")
     for k, (ms, n) in stages.items():
