@@ -389,7 +389,7 @@ def bench_builders(args):
     scene, cam = workload("terrain3.4M_1080p")
     dev = torch.device("cuda")
     res = {"workload": "terrain3.4M_1080p", "builders": {}}
-    for accel in ("lbvh", "lbvh_karras"):
+    for accel in ("ploc", "karras"):
         GpuScene(scene, accel=accel).close()  # first build pays one-time costs (code loading, allocation)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
