@@ -40,6 +40,8 @@ def workload(name: str):
         return s, c.resized(3840, 2160)
     if name == "terrain212k_1080p":
         return sg.make_terrain_1080p()
+    if name == "spheres8_256":
+        return sg.make_spheres_scene()
     raise SystemExit(f"unknown workload {name}")
 
 
