@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -923,8 +924,12 @@ hipError_t copy_to_host(const void* src, void* host_dst_device_view, size_t byte
 }
 
 int trace_grid_size(int device, int blocks_per_cu, bool multi) {
+  // per device (the current one, which the occupancy query reads): CUs and workgroups per CU of the
+  // single-scene and batch traversal kernels, looked up once; renders may come from several threads
+  static std::mutex lock;
   static int cached_cus[64] = {0}, cached_occ[64][2] = {{0}};
   if (device < 0 || device >= 64) return kMaxTraceBlocks;
+  std::lock_guard<std::mutex> guard(lock);
   if (!cached_cus[device]) {
     hipDeviceProp_t prop;
     int cus = 256;

@@ -101,8 +101,32 @@ def run_compare(args):
                "uncertified": res["uncertified"], "max_err": res["max_err"],
                "max_rel_t_err": res.get("max_rel_t_err"), "tie_ids": res["tie_ids"],
                "oracle_rays": int(np.asarray(o["ray_counts"]).sum()), "passed": res["passed"]}
+    if getattr(args, "details", False):
+        summary["tie_details"] = tie_details(gpu, orc, o["samples"])
     print(json.dumps(summary), flush=True)
     return summary
+
+
+def tie_details(gpu: dict, orc: dict, samples) -> list:
+    """For each tie path: the first decision where the GPU and the oracle differ, with the oracle's margin."""
+    from tests.parity import CONTRIB_MIN
+    prim = gpu["path_prims"] != orc["path_prims"]
+    sh = (gpu["shadow_state"] != orc["shadow_state"]) & (orc["shadow_contrib"] > CONTRIB_MIN)
+    tie = prim.any(axis=1) | sh.reshape(len(prim), -1).any(axis=1)
+    out = []
+    for k in np.nonzero(tie)[0]:
+        for d in range(prim.shape[1]):
+            if sh[k, d].any() and not prim[k, :d + 1].any():
+                ls = np.nonzero(sh[k, d])[0]
+                out.append({"path": int(samples[k]), "depth": d, "kind": "shadow", "lights": ls.tolist(),
+                            "margin": float(orc["shadow_margin"][k, d, ls].min()),
+                            "contribution": float(orc["shadow_contrib"][k, d, ls].max())})
+                break
+            if prim[k, d]:
+                out.append({"path": int(samples[k]), "depth": d, "kind": "hit", "oracle": int(orc["path_prims"][k, d]),
+                            "gpu": int(gpu["path_prims"][k, d]), "margin": float(orc["hit_margin"][k, d])})
+                break
+    return out
 
 
 def main():
@@ -118,6 +142,7 @@ def main():
     c = sub.add_parser("compare")
     c.add_argument("--oracle", required=True)
     c.add_argument("--gpu", required=True)
+    c.add_argument("--details", action="store_true", help="list the first divergent decision of every tie")
     args = ap.parse_args()
     if args.cmd == "oracle":
         run_oracle(args)

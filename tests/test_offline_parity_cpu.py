@@ -61,8 +61,12 @@ def test_compare_counts_ties_and_refuses_mismatched_inputs(tmp_path):
     def wrong_primitive(g):  # a hit id the oracle does not certify: a real mismatch
         g["path_prims"][hit, 0] = (g["path_prims"][hit, 0] + 1) % 9
     bad = _gpu_file(tmp, orc, "bad.npz", mutate=wrong_primitive)
-    s = op.run_compare(argparse.Namespace(oracle=orc, gpu=bad))
+    s = op.run_compare(argparse.Namespace(oracle=orc, gpu=bad, details=True))
     assert s["ties"] == 1 and not s["passed"] and s["tie_ids"] == [int(o["samples"][hit])]
+    assert s["tie_details"] == [{"path": int(o["samples"][hit]), "depth": 0, "kind": "hit",
+                                 "oracle": int(o["path_prims"][hit, 0]),
+                                 "gpu": int((o["path_prims"][hit, 0] + 1) % 9),
+                                 "margin": float(o["hit_margin"][hit, 0])}]
     assert s["uncertified"] and s["uncertified"][0][0] == int(o["samples"][hit])
 
     def brighter(g):

@@ -77,3 +77,41 @@ def test_noalloc_rejects_bad_arguments(torch_cuda):
                                     None, None)
     assert ei.value.status == rt.RT_ERR_INVALID_ARGUMENT
     gs.close()
+
+
+def test_noalloc_render_replays_in_a_graph(torch_cuda):
+    """The use the entry point exists for: a render captured into a HIP graph (nothing is allocated while
+    capturing) and replayed, with eager work and synchronisations between the replays; every replay gives the
+    bytes of the eager render."""
+    torch = torch_cuda
+    from paper_1702_01530_amd import rt
+    from paper_1702_01530_amd.stereo import GpuScene, alloc_outputs, output_struct, render_stereo
+    scene, cam = sg.make_small_terrain(seed=5, grid=20, n_spheres=3, level=1, lights=2, depth=3)
+    cam = cam.resized(96, 64)
+    gs = GpuScene(scene)
+    ref = render_stereo(gs, cam, path_ids=True)
+    torch.cuda.synchronize()
+    out = alloc_outputs(cam, gs.num_lights, gs.device, path_ids=True, counts=False)
+    st, camst = output_struct(out), rt.make_camera_struct(cam)
+    s = torch.cuda.Stream()
+    # first call on the device outside the capture: it looks up the scratch and the launch grid
+    rt.rt_render_stereo_noalloc(gs.handle, camst, st, rt.RT_FLAG_PATH_IDS, s.cuda_stream, None)
+    s.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        rt.rt_render_stereo_noalloc(gs.handle, camst, st, rt.RT_FLAG_PATH_IDS, s.cuda_stream, None)
+    other = sg.make_spheres_scene()
+    g2 = GpuScene(other[0])
+    for rep in range(3):
+        for k in ("radiance", "hit_t"):
+            out[k].fill_(-7.0)
+        render_stereo(g2, other[1].resized(40, 24))  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        say(f"[noalloc graph] replay {rep}")
+        for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state"):
+            assert torch.equal(out[k], ref[k]), (rep, k)
+    del graph
+    gs.close()
+    g2.close()
