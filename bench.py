@@ -768,7 +768,7 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "triangles": scene.num_triangles, "width": cam.width,
                    "height": cam.height, "eyes": 2, "max_depth": cam.max_depth, "lights": scene.num_lights,
-                   "accel": "lbvh"},
+                   "accel": info.get("builder_name", "ploc")},
         "stereo_fps": 1e3 / ms_per_step,
         "stereo_fps_end_to_end": (1e3 / e2e_best) if e2e_best else None,
         "ms_per_step_end_to_end": e2e_best,
@@ -810,10 +810,11 @@ def main():
             f"{cb['host_nproc']}), {cb['one_thread']['value']:.5f} Mrays/s on 1 thread; a full frame would take "
             f"{cb['frame_seconds']:.0f} s (extrapolated)")
         from tests.parity import compare
-        pr = compare(g_ids, orc, allow_min_one=False)
+        pr = compare(g_ids, orc, allow_min_one=False, scene=scene, cam=cam)
         res["parity"] = {"n": pr["n"], "ties": pr["ties"], "tie_rate_upper95": pr["tie_rate_upper95"],
-                         "uncertified": len(pr["uncertified"]), "max_err": pr["max_err"],
-                         "max_rel_t_err": pr.get("max_rel_t_err"), "passed": pr["passed"],
+                         "uncertified": len(pr["uncertified"]), "certified_by_shift": len(pr["certified_by_shift"]),
+                         "max_err": pr["max_err"], "max_rel_t_err": pr.get("max_rel_t_err"),
+                         "max_t_offset": pr.get("max_t_offset"), "passed": pr["passed"],
                          "timed_kernels_equal": same,
                          "sample": "the cpu_baseline sample: GPU frame with ray-tree signatures vs the FP64 oracle"}
         log(f"[bench] parity on {pr['n']} paths: ties {pr['ties']} (95% bound {pr['tie_rate_upper95']:.2e}), "

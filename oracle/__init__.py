@@ -1,7 +1,11 @@
 """FP64 brute-force stereo Whitted ray-tracing oracle (ctypes binding).
 
 TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
-benchmark's CPU-baseline leg, never by the GPU library or its binding.  The C++
+benchmark's CPU-baseline leg, never by the GPU library or its binding.
+
+``render(..., accel="bvh")`` answers the same queries through an FP64 triangle
+hierarchy instead of testing every primitive: the same radiance and signature
+(the tests check it against the brute-force mode), no margins.  The C++
 source (``oracle.cpp``) shares no code with the GPU path.
 
 ``render`` returns, per sampled path (path id = eye*H*W + row*W + col):
@@ -56,7 +60,8 @@ class _Output(C.Structure):
     _fields_ = [
         ("radiance", C.c_void_p), ("hit_t", C.c_void_p), ("hit_prim", C.c_void_p), ("path_prims", C.c_void_p),
         ("shadow_state", C.c_void_p), ("hit_margin", C.c_void_p), ("shadow_margin", C.c_void_p),
-        ("shadow_contrib", C.c_void_p), ("ray_counts", C.c_int64 * 3),
+        ("shadow_contrib", C.c_void_p), ("path_t", C.c_void_p), ("hit_cos", C.c_void_p),
+        ("ray_counts", C.c_int64 * 3),
     ]
 
 
@@ -67,9 +72,13 @@ def lib():
     global _lib
     if _lib is None:
         _lib = C.CDLL(build())
-        _lib.orc_render.restype = C.c_int
-        _lib.orc_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_void_p, C.c_int64, C.c_int32,
-                                    C.POINTER(_Output)]
+        for name in ("orc_render", "orc_render_bvh"):
+            f = getattr(_lib, name)
+            f.restype = C.c_int
+            f.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_void_p, C.c_int64, C.c_int32, C.POINTER(_Output)]
+        _lib.orc_render_shifted.restype = C.c_int
+        _lib.orc_render_shifted.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_void_p, C.c_int64, C.c_int32,
+                                            C.c_int32, C.c_void_p, C.POINTER(_Output)]
         _lib.orc_primary_ray.argtypes = [C.POINTER(_Camera), C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
         _lib.orc_primary_ray.restype = None
         d = C.c_void_p
@@ -143,8 +152,15 @@ def default_threads() -> int:
     return max(1, min(16, os.cpu_count() or 1))
 
 
-def render(scene, cam, samples=None, nthreads=None) -> dict:
-    """Oracle render of the sampled paths (None: every path of both eyes)."""
+def render(scene, cam, samples=None, nthreads=None, accel="brute", t_shift=None) -> dict:
+    """Oracle render of the sampled paths (None: every path of both eyes).
+
+    accel="brute" tests every primitive for every query and returns the decision margins; accel="bvh"
+    answers the same queries through an FP64 triangle hierarchy (the same radiance and ray-tree signature,
+    margins NaN), for whole frames of large scenes.  t_shift ([n, D+1], optional) moves each path's hit
+    point at each depth along its ray by that signed distance, keeping the primitive hit."""
+    if accel not in ("brute", "bvh"):
+        raise ValueError(f"unknown accel {accel!r}")
     held = _Held()
     s = _scene_struct(scene, held)
     c = _camera_struct(cam)
@@ -162,13 +178,22 @@ def render(scene, cam, samples=None, nthreads=None) -> dict:
         "radiance": np.zeros((n, 3)), "hit_t": np.zeros(n), "hit_prim": np.zeros(n, np.int32),
         "path_prims": np.zeros((n, D1), np.int32), "shadow_state": np.zeros((n, D1, L), np.uint8),
         "hit_margin": np.zeros((n, D1)), "shadow_margin": np.zeros((n, D1, L)),
-        "shadow_contrib": np.zeros((n, D1, L)),
+        "shadow_contrib": np.zeros((n, D1, L)), "path_t": np.zeros((n, D1)), "hit_cos": np.zeros(n),
     }
     o = _Output()
     for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state", "hit_margin", "shadow_margin",
-              "shadow_contrib"):
+              "shadow_contrib", "path_t", "hit_cos"):
         setattr(o, k, _ptr(res[k]))
-    rc = lib().orc_render(C.byref(s), C.byref(c), _ptr(samp), n, int(nthreads or default_threads()), C.byref(o))
+    nt = int(nthreads or default_threads())
+    if t_shift is not None:
+        shift = np.ascontiguousarray(t_shift, dtype=np.float64)
+        if shift.shape != (n, D1) or not np.isfinite(shift).all():
+            raise ValueError(f"t_shift must be finite with shape {(n, D1)}")
+        rc = lib().orc_render_shifted(C.byref(s), C.byref(c), _ptr(samp), n, nt, int(accel == "bvh"),
+                                      _ptr(shift), C.byref(o))
+    else:
+        fn = lib().orc_render if accel == "brute" else lib().orc_render_bvh
+        rc = fn(C.byref(s), C.byref(c), _ptr(samp), n, nt, C.byref(o))
     if rc != 0:
         raise ValueError("oracle render rejected its arguments")
     res["ray_counts"] = np.array(list(o.ray_counts), np.int64)

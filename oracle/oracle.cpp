@@ -28,8 +28,12 @@
 // margin: how far the inputs sit from flipping it.  Tests use the margins to
 // certify pixels where FP32 and FP64 legitimately choose differently.  Near-miss
 // margins of 1e-2 and above are not recorded (reported as +inf): certification
-// only ever uses margins below 1e-3.
+// only ever uses margins below 1e-3.  A shifted render moves chosen hit points
+// along their rays before the path goes on, so that a test can ask whether a
+// different choice further down a path is the exact answer for a hit point a
+// stated distance from the exact one (a backward-error check).
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdint>
@@ -94,6 +98,8 @@ typedef struct {
   double* hit_margin;       // [n][D+1] closest-hit decision margin (inf when not spawned)
   double* shadow_margin;    // [n][D+1][L] cast and occlusion decision margin
   double* shadow_contrib;   // [n][D+1][L] radiance the light's decision is worth at the pixel
+  double* path_t;           // [n][D+1] closest-hit distance per depth; +inf on a miss or not spawned
+  double* hit_cos;          // [n] |cos| of the angle between the primary ray and the hit's normal; NaN on a miss
   int64_t ray_counts[3];    // out: primary, reflection, shadow rays traced
 } orc_output;
 
@@ -330,6 +336,201 @@ bool any_hit(const Scene& sc, V3 O, V3 d, double tmin, double tmax, int64_t excl
 }
 
 // ---------------------------------------------------------------------------------------------
+// Triangle hierarchy for the second mode: a binary tree built top-down by splitting the triangles
+// at the median centroid on the longest axis of the centroid bounds, at most four triangles per
+// leaf.  Node boxes bound the triangles' vertices (exact in FP64, the inputs being FP32) and are
+// padded outwards by kBvhPad times the scene's largest coordinate, far more than the rounding of
+// the slab and triangle arithmetic, so a ray that hits a triangle at t enters every box above it at
+// or before t.
+// ---------------------------------------------------------------------------------------------
+
+const double kBvhPad = 1e-9;
+
+struct Bvh {
+  struct Node {
+    double lo[3], hi[3];
+    int64_t left;   // inner node: left child; leaf: position of its first triangle in `order`
+    int32_t count;  // triangles in a leaf, 0 for an inner node
+    int64_t right;  // inner node: right child
+  };
+  std::vector<Node> nodes;
+  std::vector<int64_t> order;  // triangle ids in leaf order
+};
+
+Bvh build_bvh(const Scene& sc) {
+  Bvh b;
+  const int64_t T = sc.T;
+  if (T == 0) return b;
+  std::vector<V3> cen(static_cast<size_t>(T));
+  double big = 0.0;
+  for (int64_t i = 0; i < T; ++i) {
+    const Tri& t = sc.tris[size_t(i)];
+    V3 v1 = t.v0 + t.e1, v2 = t.v0 + t.e2;
+    cen[size_t(i)] = (1.0 / 3.0) * (t.v0 + v1 + v2);
+    for (V3 v : {t.v0, v1, v2})
+      big = std::fmax(big, std::fmax(std::fabs(v.x), std::fmax(std::fabs(v.y), std::fabs(v.z))));
+  }
+  const double pad = kBvhPad * (1.0 + big);
+  b.order.resize(size_t(T));
+  for (int64_t i = 0; i < T; ++i) b.order[size_t(i)] = i;
+  struct Task {
+    int64_t node, begin, end;
+  };
+  b.nodes.push_back({});
+  std::vector<Task> todo{{0, 0, T}};
+  while (!todo.empty()) {
+    Task k = todo.back();
+    todo.pop_back();
+    Bvh::Node nd;
+    for (int a = 0; a < 3; ++a) nd.lo[a] = kInf, nd.hi[a] = -kInf;
+    double clo[3] = {kInf, kInf, kInf}, chi[3] = {-kInf, -kInf, -kInf};
+    for (int64_t i = k.begin; i < k.end; ++i) {
+      const int64_t id = b.order[size_t(i)];
+      const Tri& t = sc.tris[size_t(id)];
+      for (V3 v : {t.v0, t.v0 + t.e1, t.v0 + t.e2}) {
+        const double c[3] = {v.x, v.y, v.z};
+        for (int a = 0; a < 3; ++a) nd.lo[a] = std::fmin(nd.lo[a], c[a]), nd.hi[a] = std::fmax(nd.hi[a], c[a]);
+      }
+      const double c[3] = {cen[size_t(id)].x, cen[size_t(id)].y, cen[size_t(id)].z};
+      for (int a = 0; a < 3; ++a) clo[a] = std::fmin(clo[a], c[a]), chi[a] = std::fmax(chi[a], c[a]);
+    }
+    for (int a = 0; a < 3; ++a) nd.lo[a] -= pad, nd.hi[a] += pad;
+    if (k.end - k.begin <= 4) {
+      nd.left = k.begin;
+      nd.count = int32_t(k.end - k.begin);
+      nd.right = -1;
+      b.nodes[size_t(k.node)] = nd;
+      continue;
+    }
+    int axis = 0;
+    for (int a = 1; a < 3; ++a)
+      if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+    const int64_t mid = (k.begin + k.end) / 2;
+    auto key = [&](int64_t id) {
+      const V3& c = cen[size_t(id)];
+      return axis == 0 ? c.x : (axis == 1 ? c.y : c.z);
+    };
+    std::nth_element(b.order.begin() + k.begin, b.order.begin() + mid, b.order.begin() + k.end,
+                     [&](int64_t x, int64_t y) { return key(x) < key(y) || (key(x) == key(y) && x < y); });
+    nd.count = 0;
+    nd.left = int64_t(b.nodes.size());
+    nd.right = nd.left + 1;
+    b.nodes[size_t(k.node)] = nd;
+    b.nodes.push_back({});
+    b.nodes.push_back({});
+    todo.push_back({nd.left, k.begin, mid});
+    todo.push_back({nd.right, mid, k.end});
+  }
+  return b;
+}
+
+// Parametric interval where the ray is inside the box, clipped to [tmin, tmax]; false if empty.
+inline bool enter_box(const Bvh::Node& n, V3 O, V3 d, double tmin, double tmax, double* t_enter) {
+  const double o[3] = {O.x, O.y, O.z}, dd[3] = {d.x, d.y, d.z};
+  double t0 = tmin, t1 = tmax;
+  for (int a = 0; a < 3; ++a) {
+    if (dd[a] == 0.0) {
+      if (o[a] < n.lo[a] || o[a] > n.hi[a]) return false;
+      continue;
+    }
+    double ta = (n.lo[a] - o[a]) / dd[a], tb = (n.hi[a] - o[a]) / dd[a];
+    if (ta > tb) std::swap(ta, tb);
+    t0 = std::fmax(t0, ta);
+    t1 = std::fmin(t1, tb);
+  }
+  *t_enter = t0;
+  return t0 <= t1;
+}
+
+// Closest hit through the tree: the same candidates and tie rule as closest_hit, no margin.
+Hit closest_hit_bvh(const Scene& sc, const Bvh& b, V3 O, V3 d, double tmin, int64_t exclude) {
+  Hit best;
+  auto consider = [&](int64_t id, bool hit, double t) {
+    if (hit && (t < best.t || (t == best.t && id < best.prim))) best.t = t, best.prim = id;
+  };
+  if (!b.nodes.empty()) {
+    std::vector<int64_t> stack{0};
+    while (!stack.empty()) {
+      const Bvh::Node& n = b.nodes[size_t(stack.back())];
+      stack.pop_back();
+      double te;
+      if (!enter_box(n, O, d, tmin, best.t, &te)) continue;
+      if (n.count > 0) {
+        for (int64_t i = n.left; i < n.left + n.count; ++i) {
+          const int64_t id = b.order[size_t(i)];
+          if (id == exclude) continue;
+          double t = kInf, u, v, m;
+          bool h = hit_triangle(sc.tris[size_t(id)], O, d, tmin, kInf, &t, &u, &v, &m);
+          consider(id, h, t);
+        }
+        continue;
+      }
+      double tl = 0.0, tr = 0.0;
+      const bool hl = enter_box(b.nodes[size_t(n.left)], O, d, tmin, best.t, &tl);
+      const bool hr = enter_box(b.nodes[size_t(n.right)], O, d, tmin, best.t, &tr);
+      if (hl && hr) {  // nearer child on top
+        stack.push_back(tl <= tr ? n.right : n.left);
+        stack.push_back(tl <= tr ? n.left : n.right);
+      } else if (hl) {
+        stack.push_back(n.left);
+      } else if (hr) {
+        stack.push_back(n.right);
+      }
+    }
+  }
+  for (int64_t i = 0; i < sc.S; ++i) {
+    int64_t id = sc.T + i;
+    if (id == exclude) continue;
+    double t = kInf, m;
+    bool h = hit_sphere(sc.sph_c[size_t(i)], sc.sph_r[size_t(i)], O, d, tmin, kInf, &t, &m);
+    consider(id, h, t);
+  }
+  for (int64_t i = 0; i < sc.P; ++i) {
+    int64_t id = sc.T + sc.S + i;
+    if (id == exclude) continue;
+    double t = kInf, m;
+    bool h = hit_plane(sc.pl_n[size_t(i)], sc.pl_d[size_t(i)], O, d, tmin, kInf, &t, &m);
+    consider(id, h, t);
+  }
+  best.margin = std::numeric_limits<double>::quiet_NaN();
+  return best;
+}
+
+// Occlusion through the tree: the same yes/no as any_hit, no margin.
+bool any_hit_bvh(const Scene& sc, const Bvh& b, V3 O, V3 d, double tmin, double tmax, int64_t exclude) {
+  for (int64_t i = 0; i < sc.S; ++i) {
+    int64_t id = sc.T + i;
+    double t = kInf, m;
+    if (id != exclude && hit_sphere(sc.sph_c[size_t(i)], sc.sph_r[size_t(i)], O, d, tmin, tmax, &t, &m)) return true;
+  }
+  for (int64_t i = 0; i < sc.P; ++i) {
+    int64_t id = sc.T + sc.S + i;
+    double t = kInf, m;
+    if (id != exclude && hit_plane(sc.pl_n[size_t(i)], sc.pl_d[size_t(i)], O, d, tmin, tmax, &t, &m)) return true;
+  }
+  if (b.nodes.empty()) return false;
+  std::vector<int64_t> stack{0};
+  while (!stack.empty()) {
+    const Bvh::Node& n = b.nodes[size_t(stack.back())];
+    stack.pop_back();
+    double te;
+    if (!enter_box(n, O, d, tmin, tmax, &te)) continue;
+    if (n.count > 0) {
+      for (int64_t i = n.left; i < n.left + n.count; ++i) {
+        const int64_t id = b.order[size_t(i)];
+        if (id == exclude) continue;
+        double t = kInf, u, v, m;
+        if (hit_triangle(sc.tris[size_t(id)], O, d, tmin, tmax, &t, &u, &v, &m)) return true;
+      }
+      continue;
+    }
+    stack.push_back(n.right);
+    stack.push_back(n.left);
+  }
+  return false;
+}
+
+// ---------------------------------------------------------------------------------------------
 // Stereo camera (off-axis pair)
 // ---------------------------------------------------------------------------------------------
 
@@ -377,12 +578,15 @@ void primary_ray(const Camera& cam, int eye, int i, int j, V3* O, V3* d) {
 struct PathRecord {
   V3 radiance;
   double hit_t;
+  double hit_cos = std::numeric_limits<double>::quiet_NaN();
   int32_t hit_prim;
   int32_t* path_prims;
   uint8_t* shadow_state;
   double* hit_margin;
   double* shadow_margin;
   double* shadow_contrib;
+  double* path_t;
+  const double* t_shift;  // null, or [D+1] distances added to each depth's hit distance
   int64_t n_refl = 0, n_shadow = 0;
 };
 
@@ -390,6 +594,7 @@ struct Tracer {
   const Scene& sc;
   int D;
   int L;
+  const Bvh* bvh;  // null: brute force with margins
 
   uint32_t material_of(int64_t prim) const {
     if (prim < sc.T) return sc.tri_mat[size_t(prim)];
@@ -411,17 +616,21 @@ struct Tracer {
 
   // Radiance arriving along ray (O, d) at recursion depth `depth`.
   V3 trace(V3 O, V3 d, int depth, double tmin, int64_t exclude, V3 throughput, PathRecord& rec) const {
-    Hit h = closest_hit(sc, O, d, tmin, exclude);
+    Hit h = bvh ? closest_hit_bvh(sc, *bvh, O, d, tmin, exclude) : closest_hit(sc, O, d, tmin, exclude);
     rec.path_prims[depth] = int32_t(h.prim);
     rec.hit_margin[depth] = h.margin;
+    rec.path_t[depth] = h.t;
     if (depth == 0) {
       rec.hit_t = h.t;
       rec.hit_prim = int32_t(h.prim);
     }
     if (h.prim < 0) return sc.background;
 
-    V3 P = O + h.t * d;
+    // A shifted hit point (for backward-error checks) moves along the ray; the primitive stays.
+    double th = rec.t_shift ? h.t + rec.t_shift[depth] : h.t;
+    V3 P = O + th * d;
     V3 Ng = geometric_normal(h.prim, P);
+    if (depth == 0) rec.hit_cos = std::fabs(dot(Ng, d)) / (length(Ng) * length(d));
     V3 N = dot(Ng, d) > 0.0 ? -1.0 * Ng : Ng;
     V3 V = -1.0 * d;
     const Scene::Mat& m = sc.mats[material_of(h.prim)];
@@ -442,8 +651,9 @@ struct Tracer {
         V3 term = mul(lt.I, ndl * m.kd + spec * m.ks);
         V3 w = mul(term, throughput);
         rec.shadow_contrib[k] = std::fmax(std::fabs(w.x), std::fmax(std::fabs(w.y), std::fabs(w.z)));
-        double occ_margin;
-        bool occ = any_hit(sc, P, Ld, kSecondaryTmin, dist, h.prim, &occ_margin);
+        double occ_margin = std::numeric_limits<double>::quiet_NaN();
+        bool occ = bvh ? any_hit_bvh(sc, *bvh, P, Ld, kSecondaryTmin, dist, h.prim)
+                       : any_hit(sc, P, Ld, kSecondaryTmin, dist, h.prim, &occ_margin);
         rec.n_shadow++;
         rec.shadow_margin[k] = std::fmin(cast_margin, occ_margin);
         rec.shadow_state[k] = occ ? 1 : 2;
@@ -468,24 +678,19 @@ struct Tracer {
   }
 };
 
-}  // namespace
-
-extern "C" {
-
-// Renders the sampled paths (path id = eye*H*W + row*W + col; NULL = all 2*H*W
-// of them) with `nthreads` worker threads pulling rows of work dynamically.
-// Returns 0 on success, -1 on invalid arguments.
-int orc_render(const orc_scene* scene_in, const orc_camera* cam_in, const int64_t* samples, int64_t n,
-               int32_t nthreads, orc_output* out) {
+int render_paths(const orc_scene* scene_in, const orc_camera* cam_in, const int64_t* samples, int64_t n,
+                 int32_t nthreads, bool use_bvh, const double* t_shift, orc_output* out) {
   if (!scene_in || !cam_in || !out || cam_in->width <= 0 || cam_in->height <= 0 || cam_in->max_depth < 0)
     return -1;
   Scene sc = load_scene(scene_in);
   Camera cam = make_camera(cam_in);
+  Bvh bvh;
+  if (use_bvh) bvh = build_bvh(sc);
   const int64_t HW = int64_t(cam.W) * cam.H;
   const int64_t total = samples ? n : 2 * HW;
   const int D = cam.D;
   const int L = int(sc.lights.size());
-  Tracer tracer{sc, D, L};
+  Tracer tracer{sc, D, L, use_bvh ? &bvh : nullptr};
   std::atomic<int64_t> next{0}, n_refl{0}, n_shadow{0};
   const int64_t chunk = 4;
   auto worker = [&]() {
@@ -505,9 +710,12 @@ int orc_render(const orc_scene* scene_in, const orc_camera* cam_in, const int64_
         rec.hit_margin = out->hit_margin + s * (D + 1);
         rec.shadow_margin = out->shadow_margin + s * (D + 1) * L;
         rec.shadow_contrib = out->shadow_contrib + s * (D + 1) * L;
+        rec.path_t = out->path_t + s * (D + 1);
+        rec.t_shift = t_shift ? t_shift + s * (D + 1) : nullptr;
         for (int k = 0; k <= D; ++k) {
           rec.path_prims[k] = -2;
           rec.hit_margin[k] = kInf;
+          rec.path_t[k] = kInf;
         }
         for (int k = 0; k < (D + 1) * L; ++k) {
           rec.shadow_state[k] = 0;
@@ -521,6 +729,7 @@ int orc_render(const orc_scene* scene_in, const orc_camera* cam_in, const int64_
         out->radiance[3 * s + 1] = Lr.y;
         out->radiance[3 * s + 2] = Lr.z;
         out->hit_t[s] = rec.hit_t;
+        out->hit_cos[s] = rec.hit_cos;
         out->hit_prim[s] = rec.hit_prim;
         my_refl += rec.n_refl;
         my_shadow += rec.n_shadow;
@@ -538,6 +747,35 @@ int orc_render(const orc_scene* scene_in, const orc_camera* cam_in, const int64_
   out->ray_counts[1] = n_refl.load();
   out->ray_counts[2] = n_shadow.load();
   return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Renders the sampled paths (path id = eye*H*W + row*W + col; NULL = all 2*H*W of them) with
+// `nthreads` worker threads pulling rows of work dynamically, testing every primitive for every
+// query.  Returns 0 on success, -1 on invalid arguments.
+int orc_render(const orc_scene* scene_in, const orc_camera* cam_in, const int64_t* samples, int64_t n,
+               int32_t nthreads, orc_output* out) {
+  return render_paths(scene_in, cam_in, samples, n, nthreads, false, nullptr, out);
+}
+
+// The same render through the triangle hierarchy: the same radiance and ray-tree signature; the
+// margins are NaN (not computed).
+int orc_render_bvh(const orc_scene* scene_in, const orc_camera* cam_in, const int64_t* samples, int64_t n,
+                   int32_t nthreads, orc_output* out) {
+  return render_paths(scene_in, cam_in, samples, n, nthreads, true, nullptr, out);
+}
+
+// Either render with the hit point of sampled path s at depth k moved along its ray by
+// t_shift[s*(D+1) + k] (a signed distance; the primitive hit is kept).  Used to ask whether a
+// different choice further down the path is what exact arithmetic gives for a hit point within a
+// stated distance of the exact one.  accel: 0 brute force (with margins), 1 hierarchy.
+int orc_render_shifted(const orc_scene* scene_in, const orc_camera* cam_in, const int64_t* samples, int64_t n,
+                       int32_t nthreads, int32_t accel, const double* t_shift, orc_output* out) {
+  if ((accel != 0 && accel != 1) || !t_shift) return -1;
+  return render_paths(scene_in, cam_in, samples, n, nthreads, accel == 1, t_shift, out);
 }
 
 // Single primary ray, for camera checks.

@@ -109,23 +109,20 @@ def run_compare(args):
 
 def tie_details(gpu: dict, orc: dict, samples) -> list:
     """For each tie path: the first decision where the GPU and the oracle differ, with the oracle's margin."""
-    from tests.parity import CONTRIB_MIN
+    from tests.parity import CONTRIB_MIN, first_divergence
     prim = gpu["path_prims"] != orc["path_prims"]
     sh = (gpu["shadow_state"] != orc["shadow_state"]) & (orc["shadow_contrib"] > CONTRIB_MIN)
     tie = prim.any(axis=1) | sh.reshape(len(prim), -1).any(axis=1)
     out = []
     for k in np.nonzero(tie)[0]:
-        for d in range(prim.shape[1]):
-            if sh[k, d].any() and not prim[k, :d + 1].any():
-                ls = np.nonzero(sh[k, d])[0]
-                out.append({"path": int(samples[k]), "depth": d, "kind": "shadow", "lights": ls.tolist(),
-                            "margin": float(orc["shadow_margin"][k, d, ls].min()),
-                            "contribution": float(orc["shadow_contrib"][k, d, ls].max())})
-                break
-            if prim[k, d]:
-                out.append({"path": int(samples[k]), "depth": d, "kind": "hit", "oracle": int(orc["path_prims"][k, d]),
-                            "gpu": int(gpu["path_prims"][k, d]), "margin": float(orc["hit_margin"][k, d])})
-                break
+        kind, d, ls = first_divergence(prim[k], sh[k])
+        if kind == "shadow":
+            out.append({"path": int(samples[k]), "depth": d, "kind": "shadow", "lights": ls.tolist(),
+                        "margin": float(orc["shadow_margin"][k, d, ls].min()),
+                        "contribution": float(orc["shadow_contrib"][k, d, ls].max())})
+        else:
+            out.append({"path": int(samples[k]), "depth": d, "kind": "hit", "oracle": int(orc["path_prims"][k, d]),
+                        "gpu": int(gpu["path_prims"][k, d]), "margin": float(orc["hit_margin"][k, d])})
     return out
 
 

@@ -7,8 +7,18 @@ The gate (per the tolerance the method is held to):
   * ties may be at most 1e-4 of the paths (at least one is allowed on a small
     sample), and every tie must be *certified*: the oracle's margin at the first
     decision where the two disagree is below 1e-3 (an FP32/FP64 rounding flip,
-    not a bug);
-  * on every other path, every radiance channel agrees to 1e-4 absolute.
+    not a bug), or, when the scene is at hand, the exact render makes the GPU's
+    choices up to and including that decision once one earlier hit point (or, for
+    a shadow decision, the shadow rays' own origin) is moved along its ray by at
+    most the hit-distance accuracy below -- the GPU's choice is then the exact
+    answer for a spawn point within FP32 reach of the exact one (backward error);
+  * on every other path, every radiance channel agrees to 1e-4 absolute;
+  * on every other path with a primary hit, the GPU's hit point lies within
+    1e-5 * max(1, t) of the oracle's hit surface: |dt| * |cos| where cos is the
+    angle between the ray and the surface normal.  Along the ray, an FP32
+    Moller-Trumbore distance errs by about eps/|cos| relative (its determinant is
+    proportional to cos), so at grazing incidence the along-ray error is reported
+    but not held to the bound.
 """
 from __future__ import annotations
 
@@ -20,6 +30,8 @@ TIE_BUDGET = 1e-4
 RADIANCE_TOL = 1e-4
 CERT_MARGIN = 1e-3
 CONTRIB_MIN = 1e-4
+T_TOL = 1e-5        # hit-distance accuracy, relative to max(1, t)
+SHIFT_STEPS = 16    # shifts tried on each side of a hit point, up to T_TOL * max(1, t)
 
 
 def gpu_flat(out: dict) -> dict:
@@ -39,8 +51,20 @@ def clopper_pearson_upper(k: int, n: int, conf: float = 0.95) -> float:
     return float(beta.ppf(conf, k + 1, n - k))
 
 
-def compare(g: dict, orc: dict, samples=None, tol=RADIANCE_TOL, allow_min_one=True) -> dict:
-    """Compare GPU flat outputs with an oracle result on the oracle's sample of paths."""
+def first_divergence(prim_diff_row, shadow_diff_row):
+    """(kind, depth, lights) of the first decision along a path where GPU and oracle differ, or None."""
+    for d in range(prim_diff_row.shape[0]):
+        if shadow_diff_row[d].any() and not prim_diff_row[:d + 1].any():
+            return "shadow", d, np.nonzero(shadow_diff_row[d])[0]
+        if prim_diff_row[d]:
+            return "hit", d, None
+    return None
+
+
+def compare(g: dict, orc: dict, samples=None, tol=RADIANCE_TOL, allow_min_one=True, scene=None, cam=None,
+            accel="brute", nthreads=None) -> dict:
+    """Compare GPU flat outputs with an oracle result on the oracle's sample of paths.  With the scene and
+    camera, ties that their margin does not certify are tried for the backward-error certificate."""
     idx = orc["samples"] if samples is None else np.asarray(samples)
     n = len(idx)
     rad = g["radiance"][idx].astype(np.float64)
@@ -54,19 +78,17 @@ def compare(g: dict, orc: dict, samples=None, tol=RADIANCE_TOL, allow_min_one=Tr
     err = np.abs(rad - orc["radiance"]).max(axis=1)
     nontie = ~tie
     uncertified = []
-    D1 = opp.shape[1]
     for k in np.nonzero(tie)[0]:
-        margin = None
-        for d in range(D1):
-            if shadow_diff[k, d].any() and not prim_diff[k, :d + 1].any():
-                ls = np.nonzero(shadow_diff[k, d])[0]
-                margin = float(orc["shadow_margin"][k, d, ls].min())
-                break
-            if prim_diff[k, d]:
-                margin = float(orc["hit_margin"][k, d])
-                break
-        if margin is None or not margin < CERT_MARGIN:
+        kind, d, ls = first_divergence(prim_diff[k], shadow_diff[k])
+        margin = float(orc["shadow_margin"][k, d, ls].min()) if kind == "shadow" else float(orc["hit_margin"][k, d])
+        if not margin < CERT_MARGIN:
             uncertified.append((int(idx[k]), margin))
+    shifted = {}
+    if uncertified and scene is not None and cam is not None:
+        rows = {int(idx[k]): k for k in np.nonzero(tie)[0]}
+        todo = [(rows[pid], first_divergence(prim_diff[rows[pid]], shadow_diff[rows[pid]])) for pid, _ in uncertified]
+        shifted = certify_by_shift(g, orc, idx, todo, scene, cam, accel=accel, nthreads=nthreads)
+        uncertified = [(pid, m) for pid, m in uncertified if pid not in shifted]
     n_tie = int(tie.sum())
     budget = TIE_BUDGET * n
     if allow_min_one:
@@ -74,18 +96,74 @@ def compare(g: dict, orc: dict, samples=None, tol=RADIANCE_TOL, allow_min_one=Tr
     res = {
         "n": n, "ties": n_tie, "tie_rate": n_tie / max(n, 1), "tie_budget": budget,
         "tie_rate_upper95": clopper_pearson_upper(n_tie, n) if n else 1.0,
-        "uncertified": uncertified, "max_err": float(err[nontie].max()) if nontie.any() else 0.0,
+        "uncertified": uncertified, "certified_by_shift": shifted,
+        "max_err": float(err[nontie].max()) if nontie.any() else 0.0,
         "worst": int(idx[nontie][np.argmax(err[nontie])]) if nontie.any() else -1,
         "tie_ids": [int(x) for x in idx[tie][:20]],
+        "tie_rows": np.nonzero(tie)[0],
     }
-    # primary hit distance on agreeing paths (diagnostic)
+    # primary hit distance on agreeing paths: along the ray (reported) and normal to the hit surface (held;
+    # along the ray when the oracle result carries no cosines)
     ok = nontie & (orc["hit_prim"] >= 0)
     if ok.any():
         t_g = g["hit_t"][idx][ok].astype(np.float64)
         t_o = orc["hit_t"][ok]
-        res["max_rel_t_err"] = float((np.abs(t_g - t_o) / np.maximum(1.0, t_o)).max())
-    res["passed"] = bool(n_tie <= budget and not uncertified and res["max_err"] <= tol)
+        rel = np.abs(t_g - t_o) / np.maximum(1.0, t_o)
+        res["max_rel_t_err"] = float(rel.max())
+        res["max_t_offset"] = float((rel * orc["hit_cos"][ok]).max()) if "hit_cos" in orc else res["max_rel_t_err"]
+    res["passed"] = bool(n_tie <= budget and not uncertified and res["max_err"] <= tol
+                         and res.get("max_t_offset", 0.0) <= T_TOL)
     return res
+
+
+def certify_by_shift(g, orc, idx, todo, scene, cam, accel="brute", nthreads=None) -> dict:
+    """Backward-error certificate for ties (rows of the compared sample) that their margin leaves open.
+
+    todo: [(row, (kind, depth, lights))].  For each, the path is rendered again with one hit point at a
+    depth up to the divergent one (below it, for a closest-hit decision) moved along its ray by
+    j/SHIFT_STEPS * T_TOL * max(1, t), j = +-1..+-SHIFT_STEPS.  The tie is certified when some such render
+    makes the GPU's closest-hit choices up to the divergent depth, its shadow states (where they are worth
+    more than CONTRIB_MIN) before it, and, for a shadow decision, its states at the divergent lights.
+    Returns {path id: (depth moved, signed shift)}, with the smallest such shift."""
+    import oracle
+    D1 = orc["path_prims"].shape[1]
+    fr = np.arange(1, SHIFT_STEPS + 1, dtype=np.float64) / SHIFT_STEPS
+    fr = np.concatenate([-fr[::-1], fr])
+    pid_rows, shifts, owners = [], [], []
+    for row, (kind, d, ls) in todo:
+        top = d if kind == "shadow" else d - 1
+        for e in range(top + 1):
+            te = orc["path_t"][row, e] if "path_t" in orc else np.inf
+            if not np.isfinite(te):
+                continue
+            for f in fr:
+                sh = np.zeros(D1)
+                sh[e] = f * T_TOL * max(1.0, te)
+                pid_rows.append(int(idx[row]))
+                shifts.append(sh)
+                owners.append((row, e, float(sh[e])))
+    if not pid_rows:
+        return {}
+    r = oracle.render(scene, cam, samples=np.asarray(pid_rows, np.int64), nthreads=nthreads, accel=accel,
+                      t_shift=np.asarray(shifts))
+    kinds = {row: (kind, d, ls) for row, (kind, d, ls) in todo}
+    out = {}
+    for i in sorted(range(len(owners)), key=lambda i: abs(owners[i][2])):   # the smallest shift that does it
+        row, e, sh = owners[i]
+        pid = int(idx[row])
+        if pid in out:
+            continue
+        kind, d, ls = kinds[row]
+        gp, gs = g["path_prims"][pid], g["shadow_state"][pid]
+        if not np.array_equal(r["path_prims"][i, :d + 1], gp[:d + 1]):
+            continue
+        worth = r["shadow_contrib"][i, :d] > CONTRIB_MIN
+        if (r["shadow_state"][i, :d] != gs[:d])[worth].any():
+            continue
+        if kind == "shadow" and not np.array_equal(r["shadow_state"][i, d, ls], gs[d, ls]):
+            continue
+        out[pid] = (e, sh)
+    return out
 
 
 def assert_parity(res: dict, tol=RADIANCE_TOL):
@@ -94,5 +172,32 @@ def assert_parity(res: dict, tol=RADIANCE_TOL):
     assert res["ties"] <= res["tie_budget"], msg
     assert not res["uncertified"], msg
     assert res["max_err"] <= tol, msg
-    if "max_rel_t_err" in res:
-        assert res["max_rel_t_err"] <= 1e-5, msg + f" t_err={res['max_rel_t_err']:.3g}"
+    if "max_t_offset" in res:
+        assert res["max_t_offset"] <= T_TOL, (msg + f" t_err={res['max_rel_t_err']:.3g} along the ray, "
+                                                    f"{res['max_t_offset']:.3g} normal to the surface")
+
+
+def compare_full(g: dict, scene, cam, samples=None, tol=RADIANCE_TOL, nthreads=None, say=print) -> dict:
+    """Parity over whole frames of large scenes: the oracle's hierarchy mode gives the radiance and
+    signature of every path (the same as its brute-force mode, which the CPU tests check), and the paths
+    that come out as ties are rendered again in the brute-force mode, which must agree with the hierarchy
+    mode on them, for the margins that certify them; the backward-error certificate and the hit-distance
+    check use the scene."""
+    import oracle
+    orc = oracle.render(scene, cam, samples=samples, nthreads=nthreads, accel="bvh")
+    res = compare(g, orc, samples=samples, tol=tol, allow_min_one=False)
+    rows = res["tie_rows"]
+    say(f"[parity] hierarchy oracle: {res['n']} paths, {len(rows)} ties to certify")
+    if len(rows):
+        ids = orc["samples"][rows]
+        b = oracle.render(scene, cam, samples=ids, nthreads=nthreads)
+        for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state", "shadow_contrib", "path_t",
+                  "hit_cos"):
+            if not np.array_equal(b[k], orc[k][rows], equal_nan=k == "hit_cos"):
+                raise AssertionError(f"the oracle's hierarchy and brute-force modes differ ({k}) on a tie path")
+        orc["hit_margin"][rows] = b["hit_margin"]
+        orc["shadow_margin"][rows] = b["shadow_margin"]
+    res = compare(g, orc, samples=samples, tol=tol, allow_min_one=False, scene=scene, cam=cam, accel="bvh",
+                  nthreads=nthreads)
+    res["certified_by_brute_force"] = int(len(rows))
+    return res

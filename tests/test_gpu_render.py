@@ -7,8 +7,9 @@ import pytest
 
 import oracle
 import scenegen as sg
-from tests.helpers import make_scene, material, mono_camera, f32, oracle_sampled
-from tests.parity import compare, assert_parity, gpu_flat
+from tests.helpers import make_scene, material, mono_camera, f32, oracle_sampled, coincident_scene, flat_scene, \
+    corners_scene, nested_scene
+from tests.parity import compare, compare_full, assert_parity, gpu_flat
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +44,7 @@ def check_parity(torch, scene, cam, samples=None, accel="ploc", **kw):
     assert int(out["ray_counts"][7]) == 0, "internal consistency check fired"
     g = gpu_flat(out)
     orc = oracle.render(scene, cam) if samples is None else oracle_sampled(scene, cam, samples, say=say)
-    res = compare(g, orc, **kw)
+    res = compare(g, orc, scene=scene, cam=cam, **kw)
     say(f"[parity] ties={res['ties']} max_err={res['max_err']:.3g} t_err={res.get('max_rel_t_err', 0):.3g}")
     assert_parity(res)
     gs.close()
@@ -137,7 +138,7 @@ def test_batch_equals_single_renders(torch_cuda):
     for i, (gs, cam) in enumerate(pairs):
         b = dict(batched[i])
         b["shadow_state"] = b["shadow_state"][..., :gs.num_lights]
-        res = compare(gpu_flat(b), oracle.render(scenes[id(gs)], cam))
+        res = compare(gpu_flat(b), oracle.render(scenes[id(gs)], cam), scene=scenes[id(gs)], cam=cam)
         say(f"[batch] item {i}: {cam.width}x{cam.height} D={cam.max_depth} ties={res['ties']} "
             f"max_err={res['max_err']:.3g}")
         assert_parity(res)
@@ -252,7 +253,7 @@ def test_served_results_equal_standalone_renders(torch_cuda, group_ratio):
         sig = render_stereo(scenes[sid], cam, path_ids=True)
         torch.cuda.synchronize()
         assert torch.equal(done[i].result["radiance"], sig["radiance"].cpu()), i
-        res = compare(gpu_flat(sig), oracle.render(host_scenes[sid], cam))
+        res = compare(gpu_flat(sig), oracle.render(host_scenes[sid], cam), scene=host_scenes[sid], cam=cam)
         say(f"[serve] request {i}: {cam.width}x{cam.height} ties={res['ties']} max_err={res['max_err']:.3g}")
         assert_parity(res)
     assert latency_stats(list(done.values()))["n"] == 6
@@ -300,23 +301,7 @@ def test_degenerate_scenes(torch_cuda):
 def test_coincident_and_zero_area_triangles(torch_cuda, accel):
     """Hundreds of copies of one triangle (equal Morton codes, equal boxes, exact ties in t that only the
     smaller id decides), zero-area triangles (collinear and point-like: never hit) and a mirror floor."""
-    rng = np.random.default_rng(7)
-    front = [[-1.0, 0.0, 4.0], [1.0, 0.0, 4.0], [0.0, 2.0, 4.0]]
-    tris = [front] * 300
-    for _ in range(60):
-        # zero area exactly in any precision: three points on a line parallel to an axis, integer
-        # coordinates (the edge vectors are (1,0,0) and (2,0,0), so the determinant is exactly 0), and
-        # a point repeated three times
-        a = rng.integers(-3, 4, 3).astype(np.float64) + [0, 1, 5]
-        axis = np.eye(3)[rng.integers(0, 3)]
-        tris.append([list(a), list(a + axis), list(a + 2 * axis)])
-        tris.append([list(a)] * 3)
-    tris.append([[-8, -0.5, 0], [8, -0.5, 0], [0, -0.5, 16]])
-    mats = [0] * 300 + [0] * 120 + [1]
-    scene = make_scene(tris=tris, tri_mat=mats, lights=[[0, 6, 1, 1, 1, 1], [3, 4, 2, 0.5, 0.5, 0.5]],
-                       materials=[material(), material(kd=(0.2, 0.2, 0.2), kr=(0.6, 0.6, 0.6))],
-                       ambient=(0.05,) * 3, name="coincident")
-    cam = mono_camera(center=(0, 1, 0), width=48, height=32, depth=3, baseline=0.065, convergence=4.0)
+    scene, cam = coincident_scene()
     g, orc, res = check_parity(torch_cuda, scene, cam, accel=accel, allow_min_one=False)
     ids = g["path_prims"].reshape(-1)
     assert (ids == 0).any() and (ids == 420).any()  # the front triangle and the floor are both seen
@@ -349,20 +334,7 @@ def test_flat_scene(torch_cuda, accel):
     """Every triangle in the plane y = 0 (boxes of zero height: the quantisation grid and the padding
     must still give every box a slab the rays can enter), a mirror stripe, grazing and axis-parallel
     rays."""
-    n = 24
-    tris, mats = [], []
-    for i in range(n):
-        for j in range(n):
-            x0, z0 = -6.0 + 0.5 * i, 0.5 * j
-            q = [[x0, 0.0, z0], [x0 + 0.5, 0.0, z0], [x0 + 0.5, 0.0, z0 + 0.5], [x0, 0.0, z0 + 0.5]]
-            tris += [[q[0], q[1], q[2]], [q[0], q[2], q[3]]]
-            mats += [1 if i % 6 == 0 else 0] * 2
-    scene = make_scene(tris=tris, tri_mat=mats, lights=[[0, 3, 4, 1, 1, 1], [-4, 0.5, 8, 0.6, 0.6, 0.6]],
-                       materials=[material(kd=(0.7, 0.6, 0.5), ks=(0.3, 0.3, 0.3), n=16),
-                                  material(kd=(0.1, 0.1, 0.1), kr=(0.8, 0.8, 0.8))],
-                       ambient=(0.05,) * 3, name="flat")
-    # eye height 0.25 over the plane: most rays graze it; the centre column of an odd width is axis-parallel
-    cam = mono_camera(center=(0, 0.25, -1), width=41, height=21, depth=2, baseline=0.065, convergence=3.0)
+    scene, cam = flat_scene()
     check_parity(torch_cuda, scene, cam, accel=accel)
 
 
@@ -578,7 +550,7 @@ def test_terrain3m_1080p_sampled(torch_cuda, terrain_3m):
     g = gpu_flat(out)
     del out, plain
     gs.close()
-    res = compare(g, oracle_sampled(scene, cam, samples, say=say), allow_min_one=False)
+    res = compare(g, oracle_sampled(scene, cam, samples, say=say), allow_min_one=False, scene=scene, cam=cam)
     say(f"[parity] ties={res['ties']} max_err={res['max_err']:.3g} t_err={res.get('max_rel_t_err', 0):.3g} "
         f"tie rate upper bound (95%): {res['tie_rate_upper95']:.3g}")
     assert_parity(res)
@@ -591,6 +563,44 @@ def test_terrain3m_4k_sampled(torch_cuda, terrain_3m):
     cam = cam.resized(3840, 2160)
     samples = sg.sample_paths(cam, 4096, seed=41)
     check_parity(torch_cuda, scene, cam, samples=samples, allow_min_one=False)
+
+
+def _full_frame(torch, scene, cam):
+    """Every path of a frame against the oracle (hierarchy mode, ties certified by brute force)."""
+    from paper_1702_01530_amd.stereo import GpuScene, render_stereo
+    say(f"[full frame] {scene.name} {cam.width}x{cam.height} D={cam.max_depth}: {2 * cam.width * cam.height} paths")
+    gs = GpuScene(scene)
+    out = render_stereo(gs, cam, path_ids=True)
+    torch.cuda.synchronize()
+    assert int(out["ray_counts"][7]) == 0, "internal consistency check fired"
+    g = gpu_flat(out)
+    del out
+    gs.close()
+    res = compare_full(g, scene, cam, say=say)
+    say(f"[full frame] n={res['n']} ties={res['ties']} ({res['tie_rate']:.2e}; budget {res['tie_budget']:.0f}) "
+        f"certified by brute force {res['certified_by_brute_force']}, by a shift {res['certified_by_shift']} "
+        f"max_err={res['max_err']:.3g} t_err={res.get('max_rel_t_err', 0):.3g} along the ray, "
+        f"{res.get('max_t_offset', 0):.3g} normal to the surface")
+    assert_parity(res)
+    return res
+
+
+@pytest.mark.timeout(900)
+def test_terrain3m_1080p_full_frame(torch_cuda, terrain_3m):
+    """The benchmark frame, every one of its 4,147,200 paths against the oracle."""
+    _full_frame(torch_cuda, *terrain_3m)
+
+
+@pytest.mark.timeout(900)
+def test_terrain212k_1080p_full_frame(torch_cuda, terrain_212k):
+    _full_frame(torch_cuda, *terrain_212k)
+
+
+@pytest.mark.timeout(900)
+def test_terrain3m_4k_full_frame(torch_cuda, terrain_3m):
+    """The 4K frame of the 3.4M-triangle scene, all 16,588,800 paths."""
+    scene, cam = terrain_3m
+    _full_frame(torch_cuda, scene, cam.resized(3840, 2160))
 
 
 def test_frames_in_flight_equal_single(torch_cuda, terrain_3m):
@@ -622,24 +632,7 @@ def test_corner_boxes_and_grid_ties(torch_cuda, accel):
     merge with B or between the corners has B's area; copies at other places; a grid of equal quads.
     The clustering rounds must still merge (a partner rule that broke mutual pairs here once refused
     the scene)."""
-    base = [[[2, 0, 0], [0, 2, 0], [0, 0, 2]],
-            [[0, 0, 0], [0.01, 0, 0], [0, 0.01, 0.01]],
-            [[2, 2, 2], [1.99, 2, 2], [2, 1.99, 1.99]]]
-    tris = [[[-50, -50, -50], [-49, -50, -50], [-50, -49, -49]]]
-    for off in ((0, 0, 0), (4, 0, 1), (-4, 1, 3), (2, 3, 6)):
-        tris += [[[v[0] + off[0], v[1] + off[1], v[2] + off[2]] for v in t] for t in base]
-    for i in range(12):
-        for j in range(6):
-            x, z = -6.0 + i, 8.0 + j
-            tris += [[[x, -0.5, z], [x + 1, -0.5, z], [x + 1, -0.5, z + 1]], [[x, -0.5, z], [x + 1, -0.5, z + 1],
-                                                                            [x, -0.5, z + 1]]]
-    mats = [0] * (1 + 12) + [1] * (2 * 72)
-    scene = make_scene(tris=tris, tri_mat=mats, lights=[[1, 6, -2, 1, 1, 1], [-3, 4, 3, 0.5, 0.5, 0.5]],
-                       materials=[material(kd=(0.7, 0.5, 0.3), ks=(0.3, 0.3, 0.3)),
-                                  material(kd=(0.2, 0.3, 0.2), kr=(0.5, 0.5, 0.5))],
-                       ambient=(0.05,) * 3, name="corners")
-    cam = mono_camera(center=(1, 2.5, -6), forward=(0, -0.2, 1), width=64, height=40, depth=2, baseline=0.065,
-                      convergence=8.0)
+    scene, cam = corners_scene()
     g, _, _ = check_parity(torch_cuda, scene, cam, accel=accel, allow_min_one=False)
     _, ob = render(torch_cuda, scene, cam, accel=accel, brute_force=True)
     b = gpu_flat(ob)
@@ -652,18 +645,12 @@ def test_deep_clustering_tree_falls_back_to_karras(torch_cuda):
     the input is long, too deep for the traversal stack: the build rebuilds with the Karras tree, says so,
     and the render matches the oracle and the brute-force path."""
     from paper_1702_01530_amd.stereo import GpuScene
-    tris, s = [], 1.0
-    for _ in range(200):
-        tris.append([[s, 0, 0], [0, s, 0], [0, 0, s]])
-        s *= 1.2
-    scene = make_scene(tris=tris, lights=[[3, 4, -2, 1, 1, 1]], materials=[material(kd=(0.6, 0.5, 0.4))],
-                       ambient=(0.05,) * 3, name="nested")
+    scene, cam = nested_scene()
     gs = GpuScene(scene, accel="ploc")
     info = gs.info()
     gs.close()
     say(f"[nested] builder={info['builder_name']} depth={info['bvh_depth']}")
     assert info["builder_name"] == "karras" and 3 * info["bvh_depth"] < 128
-    cam = mono_camera(center=(2, 2, -3), forward=(-0.1, -0.2, 1), width=48, height=32, depth=1)
     g, _, _ = check_parity(torch_cuda, scene, cam, accel="ploc", allow_min_one=False)
     _, ob = render(torch_cuda, scene, cam, accel="ploc", brute_force=True)
     b = gpu_flat(ob)

@@ -14,4 +14,4 @@ def test_chunked_oracle_equals_one_call():
     parts = oracle_sampled(scene, cam, samples, chunk=77, say=lambda *a: None)
     assert set(one) == set(parts)
     for k in one:
-        assert np.array_equal(one[k], parts[k]), k
+        assert np.array_equal(one[k], parts[k], equal_nan=k == "hit_cos"), k  # NaN where a ray misses
