@@ -173,7 +173,7 @@ typedef struct {
 } rt_stereo_camera;
 
 #define RT_MAX_DEPTH 8
-#define RT_MAX_COORD 1e18f /* largest |coordinate| of a triangle vertex */
+#define RT_MAX_COORD 1e12f /* largest |coordinate| of a triangle vertex */
 #define RT_MAX_PIXELS ((int64_t)1 << 28) /* width * height per eye */
 
 enum {

@@ -748,7 +748,9 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(WideArgs a) {
   // Quantise the children's boxes on the node's own grid: per axis a power-of-two step s with
   // 255 s >= the node's extent, lower corners rounded down and upper corners rounded up.  The
   // differences are formed in FP64 and nudged outwards by one FP64 ulp, so the exact grid box always
-  // contains the padded FP32 box.
+  // contains the padded FP32 box.  The node stores 2^24 s (the traversal reads each grid byte as the
+  // FP16 value q 2^-24); s >= 2^-126 and, with vertices within RT_MAX_COORD, s <= 2^34, so 2^24 s
+  // is a normal float.
   float plo[3], phi[3];
   for (int ax = 0; ax < 3; ++ax) {
     plo[ax] = INFINITY;
@@ -773,7 +775,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(WideArgs a) {
       while (ldexp(255.0, e) < ext) ++e;
     }
     const double step = ldexp(1.0, e);
-    steps[ax] = __uint_as_float(uint32_t(e + 127) << 23);  // 2^e, a normal float
+    steps[ax] = __uint_as_float(uint32_t(e + 24 + 127) << 23);  // 2^(e + 24)
     for (int k = 0; k < 4; ++k) {
       uint32_t ql = 255u, qh = 0u;
       if (r[k] != kWideEmpty) {

@@ -63,6 +63,8 @@ constexpr int kLdsNodes = kQuantNodes ? SRT_LDS_NODES : 0;
 // Small vector helpers
 // ---------------------------------------------------------------------------------------------
 
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
 __device__ inline float3 f3(float4 v) { return make_float3(v.x, v.y, v.z); }
 __device__ inline float3 operator+(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
 __device__ inline float3 operator-(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
@@ -254,14 +256,19 @@ __device__ __attribute__((always_inline)) inline void lds_read_node(const float4
 }
 
 // Nodes below `kc` are read from the LDS copy `lnodes` of the top of the tree.
-template <bool HITS_ONLY>
+template <bool HITS_ONLY, bool PERM_GRID>
 __device__ __attribute__((always_inline)) inline void node4_children(const float4* __restrict__ nodes,
                                                                      const float4* lnodes, int kc, int node,
                                                                      float3 inv, float3 oi, float tmin, float tmax,
                                                                      float (&t)[4], int (&r)[4]) {
 #if SRT_QNODE
   // Slab planes of child k on axis a are p_a + q s_a, i.e. t = q (s_a / d_a) + (p_a - o_a) / d_a; the
-  // near and far planes of an axis are picked once per node from the ray's direction sign.
+  // near and far planes of an axis are picked once per node from the ray's direction sign.  A byte q
+  // placed in the low byte of an FP16 value is the subnormal q 2^-24, exactly; one v_perm_b32 makes
+  // two such values from two grid bytes, and v_fma_mix_f32 takes one as its FP16 multiplicand.  The
+  // node stores S = 2^24 s, so q 2^-24 (S / d) = q (s / d) exactly and each plane is the same fused
+  // multiply-add, to the bit, as with q converted to FP32.  S / d is finite for every direction
+  // because vertices lie within RT_MAX_COORD.
   float4 n0, n1, n2, n3;
   if (node < kc) {
     lds_read_node(lnodes, node, n0, n1, n2, n3);
@@ -272,18 +279,37 @@ __device__ __attribute__((always_inline)) inline void node4_children(const float
     n2 = n[2];
     n3 = n[3];
   }
-  const float ax = n0.w * inv.x, ay = n3.z * inv.y, az = n3.w * inv.z;  // steps are powers of two: exact
+  const float ax = n0.w * inv.x, ay = n3.z * inv.y, az = n3.w * inv.z;  // 2^24 s / d; S is a power of two: exact
   const float bx = fmaf(n0.x, inv.x, -oi.x), by = fmaf(n0.y, inv.y, -oi.y), bz = fmaf(n0.z, inv.z, -oi.z);
   const bool px = inv.x >= 0.f, py = inv.y >= 0.f, pz = inv.z >= 0.f;
   const uint32_t qlx = __float_as_uint(n2.x), qhx = __float_as_uint(n2.y), qly = __float_as_uint(n2.z),
                  qhy = __float_as_uint(n2.w), qlz = __float_as_uint(n3.x), qhz = __float_as_uint(n3.y);
   const uint32_t nx = px ? qlx : qhx, fx = px ? qhx : qlx, ny = py ? qly : qhy, fy = py ? qhy : qly,
                  nz = pz ? qlz : qhz, fz = pz ? qhz : qlz;
+  // bytes 2j and 2j+1 of w as the FP16 pair (q 2^-24, q' 2^-24): selector byte 0x0c gives a zero byte
+  auto grid_pair = [](uint32_t w, int j) {
+    return __builtin_bit_cast(half2_t, __builtin_amdgcn_perm(0u, w, j ? 0x0c030c02u : 0x0c010c00u));
+  };
+  half2_t hnx[2], hfx[2], hny[2], hfy[2], hnz[2], hfz[2];
+  if (PERM_GRID) {
+    for (int j = 0; j < 2; ++j) {
+      hnx[j] = grid_pair(nx, j), hfx[j] = grid_pair(fx, j), hny[j] = grid_pair(ny, j), hfy[j] = grid_pair(fy, j);
+      hnz[j] = grid_pair(nz, j), hfz[j] = grid_pair(fz, j);
+    }
+  }
+  // Without PERM_GRID the bytes are converted to FP32 and scaled by s / d = 2^-24 (S / d), exact: the same
+  // planes to the bit with fewer live registers (the batch kernel also holds each lane's scene fields).
+  const float sx = ax * 0x1p-24f, sy = ay * 0x1p-24f, sz = az * 0x1p-24f;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const float xn = fmaf(float((nx >> (8 * k)) & 0xffu), ax, bx), xf = fmaf(float((fx >> (8 * k)) & 0xffu), ax, bx);
-    const float yn = fmaf(float((ny >> (8 * k)) & 0xffu), ay, by), yf = fmaf(float((fy >> (8 * k)) & 0xffu), ay, by);
-    const float zn = fmaf(float((nz >> (8 * k)) & 0xffu), az, bz), zf = fmaf(float((fz >> (8 * k)) & 0xffu), az, bz);
+    auto q = [k](const half2_t (&h)[2]) { return float((k & 1) ? h[k >> 1].y : h[k >> 1].x); };
+    auto b = [k](uint32_t w) { return float((w >> (8 * k)) & 0xffu); };
+    const float xn = PERM_GRID ? fmaf(q(hnx), ax, bx) : fmaf(b(nx), sx, bx);
+    const float xf = PERM_GRID ? fmaf(q(hfx), ax, bx) : fmaf(b(fx), sx, bx);
+    const float yn = PERM_GRID ? fmaf(q(hny), ay, by) : fmaf(b(ny), sy, by);
+    const float yf = PERM_GRID ? fmaf(q(hfy), ay, by) : fmaf(b(fy), sy, by);
+    const float zn = PERM_GRID ? fmaf(q(hnz), az, bz) : fmaf(b(nz), sz, bz);
+    const float zf = PERM_GRID ? fmaf(q(hfz), az, bz) : fmaf(b(fz), sz, bz);
     const float tn = fmaxf(fmaxf(xn, yn), fmaxf(zn, tmin));
     const float tf = fminf(fminf(xf, yf), fminf(zf, tmax));
     // HITS_ONLY: 0 for a hit child, +inf otherwise (an occlusion query needs no entry distance)
@@ -389,9 +415,12 @@ struct Best {
 // ANY = true : occlusion, stops at the first primitive with t in (tmin, best.t); best.key >= 0 if found.
 // Candidates are tested against next_up(best.t) in the closest-hit case so that an exact tie in t
 // reaches the (t, id) comparison, and boxes entered exactly at best.t are not culled.
-template <bool ANY, bool COUNT>
+template <bool ANY, bool COUNT, bool PERM_GRID>
 __device__ inline void traverse(const DevScene& sc, const float4* lnodes, int kc, float3 o, float3 d, float tmin,
                                 int exclude, bool brute, Best& best, Stack& st, uint32_t& nnodes, uint32_t& ntris) {
+  // upper end of the interval a candidate or a box must start in: best.t for an occlusion query, the
+  // next float above best.t for a closest hit; it changes only when a hit is accepted
+  float limit = ANY ? best.t : next_up(best.t);
   auto accept = [&](float t, int key, int id) -> bool {  // returns true when the traversal can stop
     if (key == exclude || !(t < INFINITY)) return false;
     if (ANY) {
@@ -404,24 +433,24 @@ __device__ inline void traverse(const DevScene& sc, const float4* lnodes, int kc
       best.t = t;
       best.key = key;
       best.id = id;
+      limit = __int_as_float(__float_as_int(t) + 1);  // t is finite here
     }
     return false;
   };
-  auto limit = [&]() { return ANY ? best.t : next_up(best.t); };
 
   for (int s = 0; s < sc.S; ++s) {
     const int key = sc.T + s;
-    if (accept(sphere_t(sc.spheres[s], o, d, tmin, limit()), key, key)) return;
+    if (accept(sphere_t(sc.spheres[s], o, d, tmin, limit), key, key)) return;
   }
   for (int p = 0; p < sc.P; ++p) {
     const int key = sc.T + sc.S + p;
-    if (accept(plane_t(sc.planes[p], o, d, tmin, limit()), key, key)) return;
+    if (accept(plane_t(sc.planes[p], o, d, tmin, limit), key, key)) return;
   }
   if (sc.T == 0) return;
   if (brute || !sc.has_bvh) {
     for (int r = 0; r < sc.T; ++r) {
       int id;
-      const float t = tri_t(sc.tris, r, o, d, tmin, limit(), &id);
+      const float t = tri_t(sc.tris, r, o, d, tmin, limit, &id);
       if (COUNT) ++ntris;
       if (accept(t, r, id)) return;
     }
@@ -442,10 +471,10 @@ __device__ inline void traverse(const DevScene& sc, const float4* lnodes, int kc
         return;
       }
       if (COUNT) ++nnodes;
-      const float tmax = limit();
+      const float tmax = limit;
       float t[4];
       int r[4];
-      node4_children<ANY>(sc.nodes, lnodes, kc, node, inv, oi, tmin, tmax, t, r);
+      node4_children<ANY, PERM_GRID>(sc.nodes, lnodes, kc, node, inv, oi, tmin, tmax, t, r);
       if (ANY) {
         // occlusion: the order of the hit children does not change the answer, so they are taken in
         // slot order (the same for every lane of the wave) without sorting: the first hit child next,
@@ -481,7 +510,7 @@ __device__ inline void traverse(const DevScene& sc, const float4* lnodes, int kc
         const int r = first + k;
         if (r == exclude) continue;  // the secondary ray's own primitive: not fetched
         int id;
-        const float t = tri_t(sc.tris, r, o, d, tmin, limit(), &id);
+        const float t = tri_t(sc.tris, r, o, d, tmin, limit, &id);
         if (COUNT) ++ntris;
         if (accept(t, r, id)) return;
       }
@@ -599,8 +628,8 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
         if (valid) {
           const DevScene sc = item_ref<MULTI>(a, k).sc;
           Best b{INFINITY, -1, 0x7fffffff};
-          traverse<false, COUNT>(sc, lnodes, kc, o, d, depth == 0 ? 0.0f : kSecondaryTmin, exclude, a.brute != 0,
-                                 b, st, c_nodes, c_tris);
+          traverse<false, COUNT, !MULTI>(sc, lnodes, kc, o, d, depth == 0 ? 0.0f : kSecondaryTmin, exclude,
+                                         a.brute != 0, b, st, c_nodes, c_tris);
           a.hit[e] = make_float2(b.t, __int_as_float(b.key));
         }
       }
@@ -626,8 +655,8 @@ __global__ __launch_bounds__(kBlock) SRT_TRACE_ATTR void k_trace(KArgs a, int de
         const float dist = sqrtf(dot(Lv, Lv));
         const float3 Ld = (1.0f / dist) * Lv;
         Best b{dist, -1, 0};
-        traverse<true, COUNT>(sc, lnodes, kc, P, Ld, kSecondaryTmin, __float_as_int(rec.w), a.brute != 0, b, st,
-                              s_nodes, s_tris);
+        traverse<true, COUNT, !MULTI>(sc, lnodes, kc, P, Ld, kSecondaryTmin, __float_as_int(rec.w), a.brute != 0, b,
+                                      st, s_nodes, s_tris);
         a.vis[sq][size_t(owner) * LS + l] = b.key < 0 ? 1 : 0;
       }
     }

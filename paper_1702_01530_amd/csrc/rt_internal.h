@@ -16,10 +16,10 @@ namespace srt {
 // ---------------------------------------------------------------------------------------------
 //
 // BVH4 node, 64 bytes = 4 x float4 (quantised child boxes, the default):
-//   n[0] = (p.x, p.y, p.z, s.x) with p the node's lower corner and s the per-axis grid steps,
-//          powers of two
+//   n[0] = (p.x, p.y, p.z, S.x) with p the node's lower corner and S = 2^24 s, s the per-axis grid
+//          steps, powers of two
 //   n[1] = child references as int bits
-//   n[2] = (lo.x, hi.x, lo.y, hi.y), n[3] = (lo.z, hi.z, s.y, s.z): 8-bit grid coordinates, child k
+//   n[2] = (lo.x, hi.x, lo.y, hi.y), n[3] = (lo.z, hi.z, S.y, S.z): 8-bit grid coordinates, child k
 //          in byte k; child k's box on an axis is [p + lo_k s, p + hi_k s] (exact values), which
 //          contains its padded FP32 box.  An empty slot has lo = 255 > hi = 0 on every axis and
 //          repeats child 0's reference, so even a spurious entry only revisits child 0.

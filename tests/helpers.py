@@ -122,9 +122,10 @@ def corners_scene():
 
 
 def nested_scene():
-    """200 nested triangles of growing size (boxes [0, 1.2^k]^3): a tree over them is a chain."""
+    """150 nested triangles of growing size (boxes [0, 1.2^k]^3, the largest within the 1e12 coordinate
+    limit): a tree over them is a chain."""
     tris, s = [], 1.0
-    for _ in range(200):
+    for _ in range(150):
         tris.append([[s, 0, 0], [0, s, 0], [0, 0, s]])
         s *= 1.2
     scene = make_scene(tris=tris, lights=[[3, 4, -2, 1, 1, 1]], materials=[material(kd=(0.6, 0.5, 0.4))],

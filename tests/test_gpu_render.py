@@ -405,6 +405,30 @@ def test_readback_matches_device(torch_cuda, size, kernel):
     gs.close()
 
 
+def test_largest_coordinates_and_axis_parallel_rays(torch_cuda):
+    """Two small triangles at opposite corners of the largest supported coordinates (+-1e12) stretch the
+    tree's top nodes to the widest grid steps, over a mirrored pyramid on a floor near the origin, seen
+    straight down: the rays of the centre column have d.x = 0 exactly and those of the centre row d.z = 0,
+    so 1/d takes its clamped value against those steps.  (A triangle as large as the coordinates would test
+    FP32 triangle arithmetic instead: its hit distance cancels from products near 1e36.)"""
+    L = 1e12
+    e = 1e7  # FP32 spacing near 1e12 is 65536
+    tris = [[[-L, -L, -L], [-L + e, -L, -L], [-L, -L + e, -L]], [[L, L, L], [L - e, L, L], [L, L - e, L]],
+            [[-5, 0, -5], [5, 0, -5], [5, 0, 5]], [[-5, 0, -5], [5, 0, 5], [-5, 0, 5]]]
+    apex, base = [0.1, 1.2, 0.05], [[-0.6, 0, -0.5], [0.7, 0, -0.4], [0.5, 0, 0.6], [-0.4, 0, 0.5]]
+    for i in range(4):
+        tris.append([base[i], base[(i + 1) % 4], apex])
+    mats = [material(kd=(0.6, 0.6, 0.5)), material(kd=(0.1, 0.1, 0.1), ks=(0.3, 0.3, 0.3), kr=(0.7, 0.7, 0.7))]
+    scene = make_scene(tris=tris, tri_mat=[0, 0, 0, 0, 1, 1, 1, 1], spheres=[[1.5, 0.5, 1.0, 0.5]], sphere_mat=[1],
+                       materials=mats, lights=[[3, 8, -2, 0.7, 0.7, 0.7], [-4, 6, 3, 0.4, 0.4, 0.4]])
+    cam = mono_camera(center=(0.3, 6.0, 0.2), forward=(0, -1, 0), up=(0, 0, 1), width=33, height=25, depth=2,
+                      hfov=50.0)
+    g, orc, res = check_parity(torch_cuda, scene, cam)
+    col = np.arange(cam.height) * cam.width + cam.width // 2
+    assert (orc["hit_prim"][col] >= 2).all() and (g["hit_prim"][col] == orc["hit_prim"][col]).all()
+    assert res["ties"] <= 1
+
+
 def test_invalid_arguments_gpu(torch_cuda):
     torch = torch_cuda
     from paper_1702_01530_amd import rt
@@ -416,7 +440,7 @@ def test_invalid_arguments_gpu(torch_cuda):
         GpuScene(bad)
     assert ei.value.status == rt.RT_ERR_INVALID_ARGUMENT and "finite" in str(ei.value)
     bad = make_scene(tris=scene.triangles.copy())
-    bad.triangles[5, 2, 0] = -2e18  # finite but beyond the largest supported coordinate
+    bad.triangles[5, 2, 0] = -2e12  # finite but beyond the largest supported coordinate (1e12)
     with pytest.raises(rt.RtError) as ei:
         GpuScene(bad)
     assert ei.value.status == rt.RT_ERR_INVALID_ARGUMENT and "magnitude" in str(ei.value)
@@ -441,7 +465,7 @@ def _decode_children(rec: np.ndarray):
         return lo, hi, refs, valid
     assert rec.nbytes == 64
     p = f[0:3].astype(np.float64)
-    step = np.array([f[3], f[14], f[15]], np.float64)
+    step = np.array([f[3], f[14], f[15]], np.float64) / 2.0 ** 24  # the node stores 2^24 times the step
     assert np.all(np.frexp(step)[0] == 0.5)  # powers of two
     refs = u[4:8].view(np.int32)
     words = [(u[8], u[9]), (u[10], u[11]), (u[12], u[13])]
