@@ -96,6 +96,7 @@ def cpu_baseline(scene, cam, rays_per_frame: int, target_s: float = 15.0):
     """The FP64 brute-force oracle as it stands, timed on the host on a seeded sample of the same frame's paths:
     with every thread of the process's CPU share (at most 16) and with one thread.  Returns the baseline
     record, and the oracle's result on the sample (for the parity check of the GPU frame)."""
+    import numpy as np
     import oracle
     import scenegen as sg
     threads = cpu_threads()
@@ -129,6 +130,23 @@ def cpu_baseline(scene, cam, rays_per_frame: int, target_s: float = 15.0):
             "one_thread": {"value": rays1 / dt1 / 1e6, "unit": "Mrays/s", "paths": n1, "rays": rays1,
                            "seconds": dt1},
             "frame_seconds": rays_per_frame / rate, "frame_seconds_is": "extrapolated from the sample's rate"}
+    # the oracle's FP64 hierarchy mode, a fairer CPU baseline: the same answers from a tree over the triangles,
+    # on a larger seeded sample that starts with the brute-force sample (checked identical on it).  The oracle
+    # times its one-thread tree build and its tracing separately.
+    nb = min(2 * cam.width * cam.height, 1 << 18)
+    more = sg.sample_paths(cam, nb, seed=97)
+    rb = oracle.render(scene, cam, samples=np.concatenate([samples, more]), nthreads=threads, accel="bvh")
+    same = all(np.array_equal(rb[k][:len(samples)], r[k], equal_nan=k == "hit_cos")
+               for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state", "shadow_contrib", "path_t",
+                         "hit_cos"))
+    raysb = int(rb["ray_counts"].sum())
+    trace_s, build_s = rb["seconds"]["trace"], rb["seconds"]["tree_build"]
+    base["hierarchy_mode"] = {
+        "value": raysb / trace_s / 1e6, "unit": "Mrays/s", "cores": threads, "paths": len(samples) + nb,
+        "rays": raysb, "trace_seconds": trace_s, "tree_build_seconds": build_s,
+        "identical_to_brute_force_on_sample": same,
+        "frame_seconds": build_s + rays_per_frame * trace_s / raysb,
+        "note": "FP64 median-split tree over the triangles, built on one thread; the trace rate excludes the build"}
     return base, r
 
 
@@ -495,7 +513,7 @@ def summarize_counters(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="terrain3.4M_1080p")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -644,6 +662,9 @@ def main():
     total_ms = run_frames(args.steps, F, per_frame=frame_ms)
     wall_s = time.perf_counter() - t_wall
     per_frame = [a.elapsed_time(b) for a, b in frame_ms]
+    # the frame time's distribution: with F frames in flight they complete in groups, so each sample is the
+    # time between the completions of frames i - F and i, over F
+    intervals = [frame_ms[i - F][1].elapsed_time(frame_ms[i][1]) / F for i in range(F, len(frame_ms))]
     ms_per_step = total_ms / args.steps
     log(f"[bench] timed {args.steps} frames, {F} in flight: {ms_per_step:.3f} ms/frame "
         f"(frame latency median {np.median(per_frame):.3f} ms), wall {wall_s:.2f} s")
@@ -746,6 +767,11 @@ def main():
         "avg_launch_ms": avg_launch_ms, "launches_per_frame": launches_per_frame,
         "timing": "HIP events around each launch on its stream, frames one at a time (isolated launches)",
         "valu": valu,
+        # the same algorithmic lane operations over the whole frame's device time (F frames in flight, so
+        # shading, resolve and the latency-bound tails of the recursion are included)
+        "whole_frame": {"achieved": ops_frame / (ms_per_step * 1e-3) / 1e12,
+                        "frac": ops_frame / (ms_per_step * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                        "trace_share_of_isolated_frame": iso_trace_ms / sum(v[0] for v in iso.values())},
         "memory": {"algorithmic_bytes_per_launch": bytes_per_launch, "node_visit_bytes": node_visit,
                    "algorithmic_gbs": bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9,
                    "dram_bytes_per_launch": traffic,
@@ -776,6 +802,10 @@ def main():
         "frames_in_flight": F,
         "ms_per_step_one_in_flight": single_ms,
         "frame_latency_ms_p50": float(np.median(per_frame)),
+        "frame_ms": {"median": float(np.median(intervals)), "p10": float(np.percentile(intervals, 10)),
+                     "p90": float(np.percentile(intervals, 90)), "n": len(intervals),
+                     "is": "(completion of frame i - completion of frame i - F) / F, F frames in flight"}
+        if intervals else None,
         "rays_per_frame": rays,
         "ray_counts": {"primary": int(cnt[0]), "mirror": int(cnt[1]), "shadow": int(cnt[2])},
         "stage_ms_per_frame": {k: v[0] / args.steps for k, v in stages.items() if v[1]},

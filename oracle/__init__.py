@@ -61,7 +61,7 @@ class _Output(C.Structure):
         ("radiance", C.c_void_p), ("hit_t", C.c_void_p), ("hit_prim", C.c_void_p), ("path_prims", C.c_void_p),
         ("shadow_state", C.c_void_p), ("hit_margin", C.c_void_p), ("shadow_margin", C.c_void_p),
         ("shadow_contrib", C.c_void_p), ("path_t", C.c_void_p), ("hit_cos", C.c_void_p),
-        ("ray_counts", C.c_int64 * 3),
+        ("ray_counts", C.c_int64 * 3), ("seconds", C.c_double * 2),
     ]
 
 
@@ -197,6 +197,7 @@ def render(scene, cam, samples=None, nthreads=None, accel="brute", t_shift=None)
     if rc != 0:
         raise ValueError("oracle render rejected its arguments")
     res["ray_counts"] = np.array(list(o.ray_counts), np.int64)
+    res["seconds"] = {"tree_build": float(o.seconds[0]), "trace": float(o.seconds[1])}
     res["samples"] = samp if samp is not None else np.arange(n, dtype=np.int64)
     return res
 

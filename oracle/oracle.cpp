@@ -35,6 +35,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -101,6 +102,7 @@ typedef struct {
   double* path_t;           // [n][D+1] closest-hit distance per depth; +inf on a miss or not spawned
   double* hit_cos;          // [n] |cos| of the angle between the primary ray and the hit's normal; NaN on a miss
   int64_t ray_counts[3];    // out: primary, reflection, shadow rays traced
+  double seconds[2];        // out: wall time of the tree build (0 in brute force) and of the tracing
 } orc_output;
 
 }  // extern "C"
@@ -684,8 +686,10 @@ int render_paths(const orc_scene* scene_in, const orc_camera* cam_in, const int6
     return -1;
   Scene sc = load_scene(scene_in);
   Camera cam = make_camera(cam_in);
+  const auto t_build = std::chrono::steady_clock::now();
   Bvh bvh;
   if (use_bvh) bvh = build_bvh(sc);
+  const auto t_trace = std::chrono::steady_clock::now();
   const int64_t HW = int64_t(cam.W) * cam.H;
   const int64_t total = samples ? n : 2 * HW;
   const int D = cam.D;
@@ -743,6 +747,9 @@ int render_paths(const orc_scene* scene_in, const orc_camera* cam_in, const int6
   for (int i = 1; i < nt; ++i) pool.emplace_back(worker);
   worker();
   for (auto& t : pool) t.join();
+  const auto t_end = std::chrono::steady_clock::now();
+  out->seconds[0] = std::chrono::duration<double>(t_trace - t_build).count();
+  out->seconds[1] = std::chrono::duration<double>(t_end - t_trace).count();
   out->ray_counts[0] = total;
   out->ray_counts[1] = n_refl.load();
   out->ray_counts[2] = n_shadow.load();

@@ -52,8 +52,9 @@ def oracle_sampled(scene, cam, samples, chunk=2048, say=print):
     for lo in range(0, len(samples), chunk):
         parts.append(oracle.render(scene, cam, samples=samples[lo:lo + chunk]))
         say(f"[oracle] {min(lo + chunk, len(samples))}/{len(samples)} paths")
-    out = {k: np.concatenate([p[k] for p in parts]) for k in parts[0] if k != "ray_counts"}
+    out = {k: np.concatenate([p[k] for p in parts]) for k in parts[0] if k not in ("ray_counts", "seconds")}
     out["ray_counts"] = sum(p["ray_counts"] for p in parts)
+    out["seconds"] = {k: sum(p["seconds"][k] for p in parts) for k in parts[0]["seconds"]}
     return out
 
 

@@ -13,5 +13,5 @@ def test_chunked_oracle_equals_one_call():
     one = oracle.render(scene, cam, samples=samples)
     parts = oracle_sampled(scene, cam, samples, chunk=77, say=lambda *a: None)
     assert set(one) == set(parts)
-    for k in one:
+    for k in set(one) - {"seconds"}:  # wall times differ
         assert np.array_equal(one[k], parts[k], equal_nan=k == "hit_cos"), k  # NaN where a ray misses
