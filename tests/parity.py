@@ -22,8 +22,6 @@ The gate (per the tolerance the method is held to):
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
 
 TIE_BUDGET = 1e-4

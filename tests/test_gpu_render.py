@@ -475,6 +475,54 @@ def _decode_children(rec: np.ndarray):
     return p[:, None] + qlo * step[:, None], p[:, None] + qhi * step[:, None], refs, valid
 
 
+def _morton_keys(tris: np.ndarray) -> np.ndarray:
+    """63-bit Morton codes of the triangles' box centroids, quantised to 2^21 cells per axis of the centroids'
+    bounds, written out in FP32 numpy (each operation rounded once) and interleaved bit by bit (x highest)."""
+    t = tris.astype(np.float32)
+    lo, hi = t.min(axis=1), t.max(axis=1)
+    c = np.float32(0.5) * lo + np.float32(0.5) * hi
+    clo, chi = c.min(axis=0), c.max(axis=0)
+    ext = chi - clo
+    cells = np.float32(2 ** 21)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        s = np.where(ext > 0, (c - clo) / ext * cells, np.float32(0.0)).astype(np.float32)
+    q = np.clip(s, np.float32(0.0), cells - np.float32(1.0)).astype(np.uint64)
+    key = np.zeros(len(t), np.uint64)
+    for b in range(21):
+        for a in range(3):
+            key |= ((q[:, a] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + 2 - a)
+    return key
+
+
+def _record_ids(gs, T: int) -> np.ndarray:
+    """Original triangle id of each of the built scene's triangle records, in storage order."""
+    info = gs.info()
+    rec_bytes = info["node_bytes"] // info["num_nodes"]
+    raw = gs._storage[gs.storage_offset:].cpu().numpy()
+    tris_off = -(-((T - 1) * rec_bytes) // 256) * 256
+    return raw[tris_off:tris_off + 48 * T].view(np.int32).reshape(T, 12)[:, 3]
+
+
+@pytest.mark.parametrize("accel", ["ploc", "karras"])
+def test_records_follow_the_stable_sort_of_morton_codes(torch_cuda, accel):
+    """Steps 3-4 of the build against their definitions: the triangle records are written in the order of a
+    stable sort of the centroids' Morton codes, the order numpy's stable argsort gives for the same codes.
+    The scenes have equal codes (duplicated triangles, whose original order must be kept) and an axis of zero
+    centroid extent (every code's bits on it zero)."""
+    from paper_1702_01530_amd.stereo import GpuScene
+    scene, _ = sg.make_small_terrain(seed=21, grid=40, n_spheres=4, level=2)
+    dup = np.concatenate([scene.triangles, scene.triangles[::7], scene.triangles[5:9]])
+    flat, _ = flat_scene()
+    for tris in (scene.triangles, dup, flat.triangles):
+        case = make_scene(tris=tris)
+        T = len(tris)
+        keys = _morton_keys(case.triangles)
+        gs = GpuScene(case, accel=accel)
+        ids = _record_ids(gs, T)
+        gs.close()
+        assert np.array_equal(ids, np.argsort(keys, kind="stable")), T
+
+
 @pytest.mark.parametrize("accel", ["ploc", "karras"])
 def test_bvh_structure(torch_cuda, accel):
     """Reads the built tree back and walks it: every node is reached once, every triangle is in exactly
