@@ -173,7 +173,11 @@ typedef struct {
 } rt_stereo_camera;
 
 #define RT_MAX_DEPTH 8
-#define RT_MAX_COORD 1e12f /* largest |coordinate| of a triangle vertex */
+/* Largest |coordinate| of a triangle vertex.  The tree's widest grid step then
+ * stays small enough that the traversal's scaled step over a clamped reciprocal
+ * direction (up to 1e20) is finite; FP32 triangle tests lose their accuracy long
+ * before this scale anyway. */
+#define RT_MAX_COORD 1e12f
 #define RT_MAX_PIXELS ((int64_t)1 << 28) /* width * height per eye */
 
 enum {

@@ -108,6 +108,35 @@ def test_chunking_and_repeat_bitwise(torch_cuda):
     gs.close()
 
 
+@pytest.mark.parametrize("accel", ["ploc", "karras"])
+def test_builds_and_renders_repeat_bitwise(torch_cuda, accel):
+    """The build and the render are deterministic despite their atomics (refit flags, clustering rounds, work
+    counters, queue appends): three builds of one scene store the same node and triangle bytes, and ten renders
+    of a frame, with their rays taken from the queues in whatever order the waves arrive, write the same bytes."""
+    torch = torch_cuda
+    from paper_1702_01530_amd.stereo import GpuScene, render_stereo
+    scene, cam = sg.make_small_terrain(seed=8, grid=64, n_spheres=6, level=2, lights=3, depth=4)
+    cam = cam.resized(160, 96)
+    stores = []
+    for _ in range(3):
+        gs = GpuScene(scene, accel=accel)
+        info = gs.info()
+        nbytes = -(-((scene.num_triangles - 1) * (info["node_bytes"] // info["num_nodes"])) // 256) * 256 \
+            + 48 * scene.num_triangles
+        torch.cuda.synchronize()
+        stores.append(gs._storage[gs.storage_offset:gs.storage_offset + nbytes].cpu())
+        gs.close()
+    assert all(torch.equal(stores[0], x) for x in stores[1:])
+    gs = GpuScene(scene, accel=accel)
+    ref = render_stereo(gs, cam, path_ids=True)
+    for _ in range(9):
+        again = render_stereo(gs, cam, path_ids=True)
+        torch.cuda.synchronize()
+        for k in ("radiance", "hit_t", "hit_prim", "path_prims", "shadow_state", "ray_counts"):
+            assert torch.equal(ref[k], again[k]), k
+    gs.close()
+
+
 def test_batch_equals_single_renders(torch_cuda):
     """A batch mixing scenes (with and without spheres/planes), resolutions, depths and light counts gives
     every item exactly its standalone render, with one pass and with many small passes."""
