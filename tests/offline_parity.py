@@ -4,11 +4,11 @@ The oracle is too slow to cover a full 1080p stereo frame of the 3.4M-triangle s
 (every query tests every primitive), so the large sample is split in two steps that meet in files:
 
     # on a host: the oracle on a seeded sample of the frame's paths (resumable, chunk by chunk)
-    python -m tests.offline_parity oracle --paths 131072 --seed 17 --out _work/orc_terrain3m_1080p.npz
+    python -m tests.offline_parity oracle --paths 131072 --seed 17 --out /tmp/orc_terrain3m_1080p.npz
     # on the GPU: the frame rendered once with ray-tree signatures, the same sample written out
-    python bench.py --dump-signature gpurun_out/gpu_sig.npz --dump-paths 131072 --dump-seed 17 ...
+    python bench.py --dump-signature /tmp/gpu_sig.npz --dump-paths 131072 --dump-seed 17 ...
     # anywhere: the comparison, with the tie rate and its 95% Clopper-Pearson upper bound
-    python -m tests.offline_parity compare --oracle _work/orc_terrain3m_1080p.npz --gpu gpurun_out/gpu_sig.npz
+    python -m tests.offline_parity compare --oracle /tmp/orc_terrain3m_1080p.npz --gpu /tmp/gpu_sig.npz
 
 The oracle step calls only the oracle and the seeded scene generator; the GPU file is never an input
 to it.
