@@ -687,6 +687,18 @@ def _full_frame(torch, scene, cam):
 
 
 @pytest.mark.timeout(900)
+def test_serving_scenes_full_frames(torch_cuda):
+    """Every resident scene of the serving workload (eight scenes of 10k to 2M triangles, log-uniform), each
+    seen from its first request's orbit pose at 640x480 per eye and depth 4: every path against the oracle."""
+    scenes, reqs = sg.make_serving_workload(n_requests=64)
+    for k, scene in enumerate(scenes):
+        cam = next(c for _, j, c in reqs if j == k).resized(640, 480)
+        cam = cam.__class__(**{**cam.__dict__, "max_depth": 4})
+        res = _full_frame(torch_cuda, scene, cam)
+        assert res["n"] == 2 * 640 * 480
+
+
+@pytest.mark.timeout(900)
 def test_terrain3m_1080p_full_frame(torch_cuda, terrain_3m):
     """The benchmark frame, every one of its 4,147,200 paths against the oracle."""
     _full_frame(torch_cuda, *terrain_3m)
