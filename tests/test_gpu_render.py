@@ -182,6 +182,35 @@ def test_batch_equals_single_renders(torch_cuda):
         x.close()
 
 
+@pytest.mark.timeout(900)
+def test_batch64_every_item_against_oracle(torch_cuda):
+    """The benchmark's batched workload (64 stereo pairs of mixed sizes, baselines and depths over 8 resident
+    scenes, 108M paths) rendered as one batch, and every path of every item compared with the oracle."""
+    torch = torch_cuda
+    from paper_1702_01530_amd.stereo import GpuScene, render_batch
+    scenes, spec = sg.make_batch_workload()
+    gss = [GpuScene(x) for x in scenes]
+    pairs = [(gss[k], cam) for k, cam in spec]
+    say(f"[batch64] {len(pairs)} pairs, {sum(2 * c.width * c.height for _, c in pairs)} paths")
+    batched = render_batch(pairs, path_ids=True)
+    torch.cuda.synchronize()
+    n = ties = 0
+    worst = 0.0
+    for i, (k, cam) in enumerate(spec):
+        b = dict(batched[i])
+        b["shadow_state"] = b["shadow_state"][..., :gss[k].num_lights]
+        g = gpu_flat(b)
+        batched[i] = None
+        res = compare_full(g, scenes[k], cam, say=lambda *a: None)
+        say(f"[batch64] item {i}: scene {k} ({scenes[k].num_triangles} tris) {cam.width}x{cam.height} "
+            f"D={cam.max_depth} ties={res['ties']} shift={len(res['certified_by_shift'])} max_err={res['max_err']:.3g}")
+        assert_parity(res)
+        n, ties, worst = n + res["n"], ties + res["ties"], max(worst, res["max_err"])
+    say(f"[batch64] {n} paths, {ties} ties ({ties / n:.2e}), max radiance error {worst:.3g}")
+    for x in gss:
+        x.close()
+
+
 def test_batch_graph_replays_match_eager(torch_cuda):
     """A captured batch replays bitwise like eager batches, with eager work and syncs between replays, and
     accepts new poses of the same shape; a different shape is refused."""
