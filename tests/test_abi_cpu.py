@@ -125,3 +125,42 @@ def test_render_argument_checks_without_device():
     assert rt.lib().rt_timer_read(None, None) == rt.RT_ERR_INVALID_ARGUMENT
     t = rt.rt_timer_create()
     rt.rt_timer_destroy(t)
+
+
+_NO_DEVICE_BUILD = r"""
+import ctypes as C, numpy as np
+from paper_1702_01530_amd import rt
+tris = np.zeros((1, 3, 3), np.float32)
+tris[0, 1, 0] = tris[0, 2, 1] = 1.0
+mat = np.zeros(1, np.uint32)
+mats, lights = (rt.rt_material * 1)(), (rt.rt_light * 1)()
+mats[0].shininess = 8.0
+lights[0].intensity[0] = 1.0
+d = rt.rt_scene_desc()
+d.num_triangles, d.num_materials, d.num_lights = 1, 1, 1
+d.triangles, d.tri_material = tris.ctypes.data, mat.ctypes.data
+d.materials, d.lights = C.cast(mats, C.POINTER(rt.rt_material)), C.cast(lights, C.POINTER(rt.rt_light))
+sb, kb = rt.rt_scene_storage_size(d)
+h = C.c_void_p()
+# storage and scratch addresses are never dereferenced: without a device the build stops at its first HIP call
+st = rt.lib().rt_scene_build(C.byref(d), C.c_void_p(1 << 20), sb, C.c_void_p(1 << 24), kb, None, C.byref(h))
+print(st, h.value is None)
+print(rt.last_error())
+"""
+
+
+def test_valid_build_without_a_device_reports_a_device_error():
+    """A valid scene build on a host without a GPU returns RT_ERR_DEVICE with the runtime's message and no
+    handle, and the process goes on (no abort).  Run in a child process so that the HIP runtime's state does
+    not carry over; skipped where a device exists (the dummy storage addresses would then reach a build)."""
+    import os
+    import subprocess
+    import sys
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a device is present")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, "-c", _NO_DEVICE_BUILD], capture_output=True, text=True, timeout=120, cwd=root)
+    assert p.returncode == 0, p.stderr
+    status, msg = p.stdout.strip().splitlines()
+    assert status.split() == [str(rt.RT_ERR_DEVICE), "True"] and "device" in msg.lower(), p.stdout
