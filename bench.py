@@ -575,6 +575,7 @@ def main():
     if args.workload == "batch64":
         with torch.cuda.stream(torch.cuda.Stream()):  # graph capture needs a stream other than the null stream
             return bench_batch(args)
+    import scenegen
     scene, cam = workload(args.workload)
     log(f"[bench] workload {args.workload}: {scene.num_triangles} triangles, {cam.width}x{cam.height} per eye, "
         f"depth {cam.max_depth}, {scene.num_lights} lights")
@@ -800,6 +801,10 @@ def main():
         "ms_per_step_end_to_end": e2e_best,
         "ms_per_step_end_to_end_by_readback": e2e or None,
         "frames_in_flight": F,
+        "environment": {"gpu": torch.cuda.get_device_name(dev),
+                        "arch": getattr(torch.cuda.get_device_properties(dev), "gcnArchName", None),
+                        "hip": torch.version.hip, "torch": torch.__version__, "host_nproc": os.cpu_count(),
+                        "scene_seed": int(scene.seed), "scene_digest": scenegen.digest(scene, cam)},
         "ms_per_step_one_in_flight": single_ms,
         "frame_latency_ms_p50": float(np.median(per_frame)),
         "frame_ms": {"median": float(np.median(intervals)), "p10": float(np.percentile(intervals, 10)),
